@@ -1,0 +1,185 @@
+/*
+ * hub.h - C ABI of libhub: the fermion-matrix solve of Hybrid Monte Carlo for the
+ * Hubbard model on the honeycomb lattice (Krieg, Luu, Ostmeyer, Papaphilippou,
+ * Urbach, "Accelerating Hybrid Monte Carlo simulations of the Hubbard model on the
+ * hexagonal lattice").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice.  L1 x L2 rhombic unit cells with a two-site basis (A = sublattice 0,
+ *   B = sublattice 1), periodic along both oblique axes, N_t time slices.  The A
+ *   site of cell (i, j) is bonded to the B sites of cells (i, j), (i-1, j) and
+ *   (i, j-1), indices mod L1, L2.  There are N = 2*L1*L2*N_t unknowns.
+ * Layout.  Every site field is stored site-major with flat index
+ *   ((t*2 + s)*L1 + i)*L2 + j, j fastest.  Complex vectors are interleaved
+ *   (re, im) float64 pairs; batched vectors are [batch][N].  phi is real float64 [N].
+ * Memory.  Every pointer marked "device" is device memory owned by the caller on
+ *   the context's device; "host" pointers are ordinary host memory.  No call frees
+ *   or retains a caller buffer beyond its return, except hub_submit (see there).
+ * Streams.  Calls taking a hipStream_t enqueue their kernels on that stream (0 =
+ *   the null stream) and are stream-ordered with the caller's other work.
+ *   hub_apply_* and hub_force return without synchronising.  hub_solve and
+ *   hub_action synchronise the stream (they read small scalars back to the host).
+ * Errors.  Every call returns a hub_status; HUB_OK is 0.  On failure
+ *   hub_last_error() returns a message for the calling thread.  No call throws.
+ *   Argument errors (null pointers, non-positive sizes, batch beyond
+ *   HUB_MAX_BATCH, non-finite couplings or tolerances) return HUB_ERR_ARG before
+ *   anything is enqueued.
+ */
+#ifndef HUB_H
+#define HUB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HUB_MAX_BATCH 64     /* systems per hub_apply_* / hub_solve / hub_force call */
+#define HUB_MAX_RESTART 20   /* largest FGMRES restart length m                      */
+
+typedef struct { double re, im; } hub_c128;
+
+/* The lattice and the step-size-weighted couplings of eq. (ferm_op):
+ * kappa_t = delta*kappa (hopping entry of M^{AB}), ms_t = delta*m_s (staggered
+ * mass on the temporal hop), delta = beta/N_t (Sec. 2). */
+typedef struct {
+  int32_t L1, L2;    /* unit cells along the two oblique axes, >= 1 */
+  int32_t Nt;        /* time slices, >= 1                           */
+  int32_t reserved;  /* must be 0                                   */
+  double kappa_t;
+  double ms_t;
+} hub_lattice;
+
+typedef enum {
+  HUB_OK = 0,
+  HUB_ERR_ARG = 1,       /* invalid argument; nothing was enqueued                  */
+  HUB_ERR_OOM = 2,       /* workspace beyond the context's HBM budget               */
+  HUB_ERR_NOCONV = 3,    /* iteration limit reached; x holds the last iterate       */
+  HUB_ERR_HIP = 4,       /* a HIP runtime call failed                               */
+  HUB_ERR_BUSY = 5,      /* request can never fit the serving budget                */
+  HUB_ERR_NOTFOUND = 6   /* unknown ticket                                          */
+} hub_status;
+
+typedef struct hub_ctx hub_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the workspace
+ * the library allocates for solves and the serving queue (0 = 75% of the device
+ * memory free at creation).  The context owns a workspace pool and, once
+ * hub_submit is first called, a serving thread. */
+hub_status hub_create(hub_ctx **ctx, int device, size_t hbm_budget_bytes);
+/* Wait for outstanding served requests, stop the serving thread, free all workspace. */
+hub_status hub_destroy(hub_ctx *ctx);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *hub_last_error(void);
+
+/* y_b = M[phi] x_b (eq. (ferm_op)) for b < batch, phi shared by the batch.
+ *   A rows: y_A(t) = -x_A(t) + s(t) (e^{i phi_A(t)} - ms_t) x_A(t-1) - kappa_t sum_bonds x_B(t)
+ *   B rows: y_B(t) = +x_B(t) - s(t) (e^{-i phi_B(t)} - ms_t) x_B(t+1) - kappa_t sum_bonds x_A(t)
+ * s = -1 on the hop that wraps the antiperiodic temporal boundary, else +1.
+ * phi: device float64 [N]; x, y: device [batch][N]; x and y must not overlap. */
+hub_status hub_apply_M(hub_ctx *ctx, const hub_lattice *lat, const double *phi,
+                       const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
+
+/* y_b = M[phi]^dagger x_b, the conjugate transpose of hub_apply_M (used for
+ * xi = M^dagger eta, eq. (eta_xi), and chi = M^dagger eta sources).  Same layout. */
+hub_status hub_apply_Mdag(hub_ctx *ctx, const hub_lattice *lat, const double *phi,
+                          const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
+
+/* y_b = (M M^dagger + mu2[b]) x_b: the Hermitian positive-definite normal operator
+ * of Sec. 3 with the Hasenbusch shift of Sec. 5.1.  mu2: host float64 [batch], each
+ * finite and >= 0.  Uses library workspace for M^dagger x (HUB_ERR_OOM if over budget). */
+hub_status hub_apply_normal(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mu2,
+                            const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
+
+typedef enum {
+  HUB_CG_FP64 = 0,        /* double-precision CG (Sec. 3)                                 */
+  HUB_FGMRES_MIXED = 1    /* FP64 flexible GMRES(m) with complex64 CG preconditioner (App. A) */
+} hub_solver;
+
+typedef struct {
+  int32_t solver;          /* hub_solver                                                    */
+  int32_t max_iter;        /* CG: iteration limit; FGMRES: limit on restart cycles          */
+  int32_t restart_m;       /* FGMRES restart length m (1..HUB_MAX_RESTART), paper: 10       */
+  int32_t inner_max_iter;  /* iteration cap of each single-precision CG                     */
+  double tol;              /* relative true-residual target ||b - A x|| / ||b||             */
+  double inner_a;          /* factor a of the inner tolerance TOL*a*|b|/ERR, paper: 5       */
+  double inner_floor;      /* smallest inner relative tolerance requested in complex64      */
+  int32_t use_x0;          /* 1: x holds an initial guess on entry; 0: start from zero      */
+  int32_t check_every;     /* iterations enqueued between convergence checks (>= 1)         */
+} hub_solve_opts;
+
+/* tol 1e-10, FP64 CG, max_iter 20000, m 10, a 5, inner_floor 1e-5, inner_max_iter 4000,
+ * use_x0 0, check_every 16. */
+void hub_default_opts(hub_solve_opts *opts);
+
+typedef struct {
+  int32_t converged;       /* 1 iff the recomputed FP64 true residual met tol             */
+  int32_t outer_iters;     /* CG: restarts after a failed true-residual check; FGMRES: cycles */
+  int32_t inner_iters;     /* CG iterations (FP64 CG) or complex64 CG iterations (FGMRES) */
+  int32_t applies;         /* FP64 applications of M M^dagger + mu2 outside CG iterations */
+  double true_rel_resid;   /* ||b - (M M^dagger + mu2) x|| / ||b||, FP64                   */
+} hub_solve_info;
+
+/* Solve (M M^dagger + mu2[b]) x_b = b_b for every b < batch with one shared phi
+ * (Sec. 3: the system (M M^dagger) eta = chi; Sec. 5.1: shifted systems; App. A:
+ * flexible GMRES).  Systems converge independently.  b, x: device [batch][N]; x is
+ * read as initial guess iff opts->use_x0.  mu2: host [batch].  info: host [batch],
+ * filled on return.  opts may be NULL (defaults).  Synchronises `stream`.
+ * Returns HUB_ERR_NOCONV if any system missed tol (x holds its last iterate). */
+hub_status hub_solve(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mu2,
+                     int32_t batch, const hub_c128 *b, hub_c128 *x, const hub_solve_opts *opts,
+                     hub_solve_info *info, hipStream_t stream);
+
+/* dSdphi_b (+)= scale * dS/dphi for S = Re chi^dagger (M M^dagger + mu2)^{-1} chi,
+ * given eta_b = (M M^dagger + mu2)^{-1} chi_b (eqs. (p_dot), (eta_xi)):
+ *   dS/dphi_{A,x,t} = 2 Im[ conj(eta_A(t)) s(t) e^{ i phi_A(t)} xi_A(t-1) ]
+ *   dS/dphi_{B,x,t} = 2 Im[ conj(eta_B(t)) s(t) e^{-i phi_B(t)} xi_B(t+1) ]
+ * with xi = M^dagger eta.  This is minus the molecular-dynamics force of eq. (p_dot).
+ * xi: device [batch][N] or NULL (then computed into library workspace).
+ * accumulate = 0 overwrites dSdphi, 1 adds to it.  dSdphi: device float64 [batch][N]. */
+hub_status hub_force(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const hub_c128 *eta,
+                     const hub_c128 *xi, double scale, int32_t accumulate, double *dSdphi,
+                     int32_t batch, hipStream_t stream);
+
+/* S_b = Re chi_b^dagger eta_b, the pseudofermion action of eq. (hamiltonian) given
+ * eta = (M M^dagger + mu2)^{-1} chi.  FP64 reduction with a fixed summation order.
+ * chi, eta: device [batch][N]; S: host float64 [batch].  Synchronises `stream`. */
+hub_status hub_action(hub_ctx *ctx, const hub_lattice *lat, const hub_c128 *chi, const hub_c128 *eta,
+                      int32_t batch, double *S, hipStream_t stream);
+
+/* Serving: one request = solve (M M^dagger + mu2) x = chi, then S = Re chi^dagger x and
+ * dS/dphi, for its own lattice, phi and shift.  Requests are admitted by workspace
+ * footprint against the budget as earlier ones retire and run batched with every
+ * other request in flight, whatever their lattice sizes (continuous batching).  The
+ * result of a request does not depend on which others share its launches.
+ * phi, chi, x_out, dSdphi_out: device memory that must stay valid and untouched
+ * until hub_poll reports done.  S_out: host, written before done is reported.
+ * dSdphi_out may be NULL (no force). */
+typedef struct {
+  hub_lattice lat;
+  double mu2;
+  const double *phi;
+  const hub_c128 *chi;
+  hub_c128 *x_out;
+  double *S_out;
+  double *dSdphi_out;
+  hub_solve_opts opts;
+} hub_request;
+
+/* Queue a request; returns at once with a ticket.  HUB_ERR_BUSY if the request alone
+ * exceeds the serving budget, HUB_ERR_ARG for invalid fields. */
+hub_status hub_submit(hub_ctx *ctx, const hub_request *req, uint64_t *ticket);
+/* Never blocks.  *done = 1 once the request's outputs are written (then info, if not
+ * NULL, is filled and the ticket is released); HUB_ERR_NOTFOUND for unknown tickets.
+ * A finished request that missed its tolerance reports done with converged = 0. */
+hub_status hub_poll(hub_ctx *ctx, uint64_t ticket, int32_t *done, hub_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUB_H */

@@ -1,0 +1,306 @@
+"""ctypes binding of libhub (include/hub.h), argument marshalling only.
+
+Torch tensors provide device memory and the current HIP stream; every step of
+the computation runs in the library's HIP kernels.  Site fields use the layout
+[batch][N_t][2][L1][L2] (complex128) or [N_t][2][L1][L2] (float64 phi).
+
+Importing this module never loads the library; the first call does, and raises
+RuntimeError if libhub.so is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhub.so")
+
+HUB_OK, HUB_ERR_ARG, HUB_ERR_OOM, HUB_ERR_NOCONV, HUB_ERR_HIP, HUB_ERR_BUSY, HUB_ERR_NOTFOUND = range(7)
+HUB_CG_FP64, HUB_FGMRES_MIXED = 0, 1
+HUB_MAX_BATCH = 64
+HUB_MAX_RESTART = 20
+STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOCONV", 4: "HUB_ERR_HIP",
+                5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
+
+SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
+           "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll"]
+
+
+class HubLattice(ctypes.Structure):
+    _fields_ = [("L1", ctypes.c_int32), ("L2", ctypes.c_int32), ("Nt", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("kappa_t", ctypes.c_double), ("ms_t", ctypes.c_double)]
+
+
+class HubSolveOpts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("restart_m", ctypes.c_int32),
+                ("inner_max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_a", ctypes.c_double),
+                ("inner_floor", ctypes.c_double), ("use_x0", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class HubSolveInfo(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("outer_iters", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("applies", ctypes.c_int32), ("true_rel_resid", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class HubRequest(ctypes.Structure):
+    _fields_ = [("lat", HubLattice), ("mu2", ctypes.c_double), ("phi", ctypes.c_void_p), ("chi", ctypes.c_void_p),
+                ("x_out", ctypes.c_void_p), ("S_out", ctypes.POINTER(ctypes.c_double)),
+                ("dSdphi_out", ctypes.c_void_p), ("opts", HubSolveOpts)]
+
+
+class HubError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhub.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1804_07195_amd.build_lib.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.hub_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_size_t]
+    L.hub_destroy.argtypes = [vp]
+    L.hub_last_error.restype = ctypes.c_char_p
+    L.hub_last_error.argtypes = []
+    for f in (L.hub_apply_M, L.hub_apply_Mdag):
+        f.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, i32, vp]
+    L.hub_apply_normal.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), vp, vp, i32, vp]
+    L.hub_default_opts.argtypes = [ctypes.POINTER(HubSolveOpts)]
+    L.hub_default_opts.restype = None
+    L.hub_solve.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
+                            ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
+    L.hub_force.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, i32, vp, i32, vp]
+    L.hub_action.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, i32, ctypes.POINTER(dbl), vp]
+    L.hub_submit.argtypes = [vp, ctypes.POINTER(HubRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.hub_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(HubSolveInfo)]
+    for name in SYMBOLS:
+        fn = getattr(L, name)
+        if name not in ("hub_last_error", "hub_default_opts"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()) -> int:
+    if status != HUB_OK and status not in allow:
+        raise HubError(status, load().hub_last_error().decode())
+    return status
+
+
+def lattice(L1: int, L2: int, Nt: int, kappa_t: float, ms_t: float = 0.0) -> HubLattice:
+    return HubLattice(int(L1), int(L2), int(Nt), 0, float(kappa_t), float(ms_t))
+
+
+def default_opts(**kw) -> HubSolveOpts:
+    o = HubSolveOpts()
+    load().hub_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "solver" and isinstance(v, str):
+            v = {"cg": HUB_CG_FP64, "fgmres": HUB_FGMRES_MIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _nsites(lat: HubLattice) -> int:
+    return 2 * lat.L1 * lat.L2 * lat.Nt
+
+
+def _vec(t: torch.Tensor, lat: HubLattice, what: str) -> int:
+    """Batch size of a complex128 device vector [batch?, N_t, 2, L1, L2] (or flat)."""
+    if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous complex128 CUDA tensor")
+    n = _nsites(lat)
+    if t.numel() % n != 0 or t.numel() == 0:
+        raise ValueError(f"{what} has {t.numel()} entries, not a multiple of N = {n}")
+    return t.numel() // n
+
+
+def _phi(t: torch.Tensor, lat: HubLattice) -> None:
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != _nsites(lat):
+        raise ValueError("phi must be a contiguous float64 CUDA tensor with N entries")
+
+
+class Context:
+    """A libhub context on one device (hub_create / hub_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.hub_create(ctypes.byref(h), int(device), int(hbm_budget_bytes)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().hub_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hub_apply_M(ctx: Context, lat: HubLattice, phi, x, y=None, stream=None):
+    """y = M[phi] x (batched over the leading dimension)."""
+    _phi(phi, lat)
+    nb = _vec(x, lat, "x")
+    y = torch.empty_like(x) if y is None else y
+    _vec(y, lat, "y")
+    _check(load().hub_apply_M(ctx.handle, ctypes.byref(lat), phi.data_ptr(), x.data_ptr(), y.data_ptr(), nb,
+                              _stream(stream)))
+    return y
+
+
+def hub_apply_Mdag(ctx: Context, lat: HubLattice, phi, x, y=None, stream=None):
+    """y = M[phi]^dagger x."""
+    _phi(phi, lat)
+    nb = _vec(x, lat, "x")
+    y = torch.empty_like(x) if y is None else y
+    _vec(y, lat, "y")
+    _check(load().hub_apply_Mdag(ctx.handle, ctypes.byref(lat), phi.data_ptr(), x.data_ptr(), y.data_ptr(), nb,
+                                 _stream(stream)))
+    return y
+
+
+def hub_apply_normal(ctx: Context, lat: HubLattice, phi, mu2, x, y=None, stream=None):
+    """y = (M M^dagger + mu2[b]) x_b."""
+    _phi(phi, lat)
+    nb = _vec(x, lat, "x")
+    mu = (ctypes.c_double * nb)(*[float(m) for m in (mu2 if hasattr(mu2, "__len__") else [mu2] * nb)])
+    y = torch.empty_like(x) if y is None else y
+    _check(load().hub_apply_normal(ctx.handle, ctypes.byref(lat), phi.data_ptr(), mu, x.data_ptr(), y.data_ptr(),
+                                   nb, _stream(stream)))
+    return y
+
+
+def hub_solve(ctx: Context, lat: HubLattice, phi, mu2, b, x=None, opts: HubSolveOpts | None = None,
+              stream=None, allow_noconv: bool = False):
+    """Solve (M M^dagger + mu2[k]) x_k = b_k.  Returns (x, [info dicts], status)."""
+    _phi(phi, lat)
+    nb = _vec(b, lat, "b")
+    mu2 = list(mu2) if hasattr(mu2, "__len__") else [mu2] * nb
+    if len(mu2) != nb:
+        raise ValueError("one shift per system")
+    mu = (ctypes.c_double * nb)(*[float(m) for m in mu2])
+    if x is None:
+        x = torch.empty_like(b)
+    _vec(x, lat, "x")
+    o = default_opts() if opts is None else opts
+    info = (HubSolveInfo * nb)()
+    st = load().hub_solve(ctx.handle, ctypes.byref(lat), phi.data_ptr(), mu, nb, b.data_ptr(), x.data_ptr(),
+                          ctypes.byref(o), info, _stream(stream))
+    _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
+    return x, [i.as_dict() for i in info], st
+
+
+def hub_force(ctx: Context, lat: HubLattice, phi, eta, xi=None, scale: float = 1.0, accumulate: bool = False,
+              out=None, stream=None):
+    """dS/dphi (float64 [batch?, N_t, 2, L1, L2]) given eta = A^{-1} chi (and optionally xi = M^dagger eta)."""
+    _phi(phi, lat)
+    nb = _vec(eta, lat, "eta")
+    if xi is not None:
+        _vec(xi, lat, "xi")
+    if out is None:
+        out = torch.zeros(eta.shape, dtype=torch.float64, device=eta.device)
+    if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != eta.numel():
+        raise ValueError("out must be a contiguous float64 tensor shaped like eta")
+    _check(load().hub_force(ctx.handle, ctypes.byref(lat), phi.data_ptr(), eta.data_ptr(),
+                            None if xi is None else xi.data_ptr(), float(scale), 1 if accumulate else 0,
+                            out.data_ptr(), nb, _stream(stream)))
+    return out
+
+
+def hub_action(ctx: Context, lat: HubLattice, chi, eta, stream=None):
+    """[Re chi_b^dagger eta_b] as a Python list (synchronises the stream)."""
+    nb = _vec(chi, lat, "chi")
+    _vec(eta, lat, "eta")
+    S = (ctypes.c_double * nb)()
+    _check(load().hub_action(ctx.handle, ctypes.byref(lat), chi.data_ptr(), eta.data_ptr(), nb, S,
+                             _stream(stream)))
+    return list(S)
+
+
+class Pending:
+    """Buffers of one served request; they must stay alive until it is done."""
+
+    def __init__(self, ticket, lat, phi, chi, x, dS, S):
+        self.ticket, self.lat, self.phi, self.chi, self.x, self.dS, self._S = ticket, lat, phi, chi, x, dS, S
+
+    @property
+    def S(self) -> float:
+        return self._S.value
+
+
+def hub_submit(ctx: Context, lat: HubLattice, mu2: float, phi, chi, x_out=None, dSdphi_out=None, force=True,
+               opts: HubSolveOpts | None = None) -> Pending:
+    """Queue solve + S + dS/dphi for one system; returns a Pending holding the ticket."""
+    _phi(phi, lat)
+    if _vec(chi, lat, "chi") != 1:
+        raise ValueError("one system per request")
+    x_out = torch.empty_like(chi) if x_out is None else x_out
+    if force and dSdphi_out is None:
+        dSdphi_out = torch.empty(phi.shape, dtype=torch.float64, device=phi.device)
+    S = ctypes.c_double(0.0)
+    req = HubRequest(lat, float(mu2), phi.data_ptr(), chi.data_ptr(), x_out.data_ptr(), ctypes.pointer(S),
+                     dSdphi_out.data_ptr() if force else None, default_opts() if opts is None else opts)
+    t = ctypes.c_uint64()
+    _check(load().hub_submit(ctx.handle, ctypes.byref(req), ctypes.byref(t)))
+    return Pending(t.value, lat, phi, chi, x_out, dSdphi_out, S)
+
+
+def hub_poll(ctx: Context, pending) -> tuple:
+    """(done, info dict or None); never blocks."""
+    ticket = pending.ticket if isinstance(pending, Pending) else int(pending)
+    done = ctypes.c_int32()
+    info = HubSolveInfo()
+    _check(load().hub_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(info)))
+    return bool(done.value), (info.as_dict() if done.value else None)
+
+
+class PseudofermionAction(torch.autograd.Function):
+    """phi -> S_b = Re chi_b^dagger (M M^dagger + mu2_b)^{-1} chi_b (eq. (hamiltonian)).
+
+    forward: hub_solve + hub_action; backward: grad_phi = sum_b grad_S[b] dS_b/dphi
+    by hub_force (xi = M^dagger eta computed inside), accumulated over the batch."""
+
+    @staticmethod
+    def forward(ctx_, phi, chi, mu2, hub_ctx: Context, lat: HubLattice, opts=None):
+        x, info, _ = hub_solve(hub_ctx, lat, phi, mu2, chi, opts=opts)
+        S = hub_action(hub_ctx, lat, chi, x)
+        ctx_.save_for_backward(phi, x)
+        ctx_.hub = (hub_ctx, lat)
+        ctx_.info = info
+        return torch.tensor(S, dtype=torch.float64, device=phi.device)
+
+    @staticmethod
+    def backward(ctx_, grad_S):
+        phi, x = ctx_.saved_tensors
+        hub_ctx, lat = ctx_.hub
+        g = grad_S.detach().to("cpu", torch.float64).tolist()
+        n = 2 * lat.L1 * lat.L2 * lat.Nt
+        xs = x.reshape(-1, n)
+        out = torch.zeros(phi.shape, dtype=torch.float64, device=phi.device)
+        for b, gb in enumerate(g):
+            hub_force(hub_ctx, lat, phi, xs[b].contiguous(), scale=gb, accumulate=True, out=out)
+        return out, None, None, None, None, None

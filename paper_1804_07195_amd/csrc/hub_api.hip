@@ -1,0 +1,502 @@
+// The C ABI of libhub (include/hub.h): argument checking, the context, the
+// synchronous calls and the serving thread behind hub_submit / hub_poll.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+
+#include "hub.h"
+#include "hub_engine.h"
+
+using namespace hub;
+
+namespace {
+
+hub_status fail(hub_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+hub_status hip_fail(hipError_t e, const char* where) {
+  return fail(HUB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HUB_HIP(expr, where)                       \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+hub_status check_lattice(const hub_lattice* lat) {
+  if (!lat) return fail(HUB_ERR_ARG, "lattice is NULL");
+  if (lat->L1 < 1 || lat->L2 < 1 || lat->Nt < 1)
+    return fail(HUB_ERR_ARG, "lattice extents must be >= 1");
+  if (lat->reserved != 0) return fail(HUB_ERR_ARG, "hub_lattice.reserved must be 0");
+  const long long n = 2LL * lat->L1 * lat->L2 * lat->Nt;
+  if (n > (1LL << 30)) return fail(HUB_ERR_ARG, "lattice too large (2*L1*L2*Nt > 2^30)");
+  if (!is_finite(lat->kappa_t) || !is_finite(lat->ms_t)) return fail(HUB_ERR_ARG, "couplings must be finite");
+  return HUB_OK;
+}
+
+hub_status check_batch(int32_t batch) {
+  if (batch < 1 || batch > HUB_MAX_BATCH) return fail(HUB_ERR_ARG, "batch must be in [1, HUB_MAX_BATCH]");
+  return HUB_OK;
+}
+
+hub_status check_opts(const hub_solve_opts& o) {
+  if (o.solver != HUB_CG_FP64 && o.solver != HUB_FGMRES_MIXED) return fail(HUB_ERR_ARG, "unknown solver");
+  if (!is_finite(o.tol) || o.tol <= 0.0 || o.tol >= 1.0) return fail(HUB_ERR_ARG, "tol must be in (0, 1)");
+  if (o.max_iter < 1) return fail(HUB_ERR_ARG, "max_iter must be >= 1");
+  if (o.restart_m < 1 || o.restart_m > HUB_MAX_RESTART) return fail(HUB_ERR_ARG, "restart_m out of range");
+  if (o.inner_max_iter < 1) return fail(HUB_ERR_ARG, "inner_max_iter must be >= 1");
+  if (!is_finite(o.inner_a) || o.inner_a <= 0.0) return fail(HUB_ERR_ARG, "inner_a must be > 0");
+  if (!is_finite(o.inner_floor) || o.inner_floor <= 0.0 || o.inner_floor >= 1.0)
+    return fail(HUB_ERR_ARG, "inner_floor must be in (0, 1)");
+  if (o.check_every < 1) return fail(HUB_ERR_ARG, "check_every must be >= 1");
+  if (o.use_x0 != 0 && o.use_x0 != 1) return fail(HUB_ERR_ARG, "use_x0 must be 0 or 1");
+  return HUB_OK;
+}
+
+static_assert(sizeof(hub_c128) == sizeof(double2), "hub_c128 layout");
+static_assert(HUB_MAX_BATCH == kMaxSys, "batch limit");
+static_assert(HUB_MAX_RESTART == kMaxRestart, "restart limit");
+
+// One served request.
+struct Ticket {
+  hub_request req;
+  System sys;
+  std::atomic<int> state{0};  // 0 queued, 1 running, 2 done
+  hub_solve_info info{};
+};
+
+class Server;
+
+}  // namespace
+
+struct hub_ctx {
+  int device = 0;
+  std::unique_ptr<Pool> pool;
+  std::mutex mu;  // serialises the synchronous calls
+  std::map<hipStream_t, std::unique_ptr<Engine>> engines;
+  std::unique_ptr<Server> server;
+  std::mutex server_mu;
+};
+
+namespace {
+
+// Continuous batching: admits queued requests whenever an engine slot and their
+// workspace fit, and advances all admitted requests together.
+class Server {
+ public:
+  explicit Server(hub_ctx* ctx) : ctx_(ctx) {
+    hipSetDevice(ctx->device);
+    hipStreamCreateWithFlags(&st_, hipStreamNonBlocking);
+    engine_.reset(new Engine(ctx->pool.get(), st_));
+    thread_ = std::thread([this] { run(); });
+  }
+  ~Server() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    thread_.join();
+    engine_.reset();
+    hipStreamDestroy(st_);
+  }
+
+  hub_status submit(const hub_request& r, uint64_t* ticket) {
+    auto t = std::make_shared<Ticket>();
+    t->req = r;
+    System& s = t->sys;
+    s.g = make_geom(r.lat);
+    s.mu2 = r.mu2;
+    s.phi = r.phi;
+    s.b = (const double2*)r.chi;
+    s.x = (double2*)r.x_out;
+    s.opts = r.opts;
+    if (Engine::workspace_bytes(s.g, s.opts) > ctx_->pool->budget())
+      return fail(HUB_ERR_BUSY, "request workspace exceeds the serving budget");
+    std::lock_guard<std::mutex> lk(mu_);
+    const uint64_t id = ++next_;
+    tickets_[id] = t;
+    queue_.push_back(id);
+    *ticket = id;
+    cv_.notify_all();
+    return HUB_OK;
+  }
+
+  hub_status poll(uint64_t id, int32_t* done, hub_solve_info* info) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = tickets_.find(id);
+    if (it == tickets_.end()) return fail(HUB_ERR_NOTFOUND, "unknown ticket");
+    if (it->second->state.load() != 2) {
+      *done = 0;
+      return HUB_OK;
+    }
+    *done = 1;
+    if (info) *info = it->second->info;
+    tickets_.erase(it);
+    return HUB_OK;
+  }
+
+ private:
+  void run() {
+    hipSetDevice(ctx_->device);
+    for (;;) {
+      std::vector<uint64_t> admit;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (queue_.empty() && engine_->count() == 0) {
+          if (stop_) return;
+          cv_.wait_for(lk, std::chrono::milliseconds(5));
+          continue;
+        }
+        // admit in arrival order while engine slots allow
+        while (!queue_.empty() && engine_->count() + (int)admit.size() < kMaxSys) {
+          admit.push_back(queue_.front());
+          queue_.pop_front();
+        }
+      }
+      std::vector<uint64_t> back;
+      for (uint64_t id : admit) {
+        if (!back.empty()) {
+          back.push_back(id);
+          continue;
+        }
+        std::shared_ptr<Ticket> t;
+        {
+          std::lock_guard<std::mutex> lk(mu_);
+          t = tickets_[id];
+        }
+        System& s = t->sys;
+        Ticket* tp = t.get();
+        s.on_done = [this, tp](System* sp) { complete(tp, sp); };
+        if (!engine_->add(&s)) {
+          back.push_back(id);  // retried once running requests release workspace
+          continue;
+        }
+        t->state = 1;
+        running_.push_back(t);
+      }
+      if (!back.empty()) {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto it = back.rbegin(); it != back.rend(); ++it) queue_.push_front(*it);
+      }
+      if (engine_->count() == 0) continue;
+      if (engine_->step() != hipSuccess) {
+        // a HIP failure: fail every running request
+        for (auto& t : running_) {
+          t->sys.status = HUB_ERR_HIP;
+          t->info = t->sys.info;
+          t->info.converged = 0;
+          engine_->remove(&t->sys);
+          t->state = 2;
+        }
+        running_.clear();
+      }
+      running_.erase(std::remove_if(running_.begin(), running_.end(),
+                                    [](const std::shared_ptr<Ticket>& t) { return t->state.load() == 2; }),
+                     running_.end());
+    }
+  }
+
+  void complete(Ticket* t, System* s) {
+    double S = 0.0;
+    const hub_request& r = t->req;
+    if (engine_->finalize(s, (const double2*)r.chi, r.dSdphi_out, &S) != hipSuccess) s->info.converged = 0;
+    if (r.S_out) *r.S_out = S;
+    t->info = s->info;
+    engine_->remove(s);
+    t->state = 2;
+  }
+
+  hub_ctx* ctx_;
+  hipStream_t st_ = nullptr;
+  std::unique_ptr<Engine> engine_;
+  std::thread thread_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  bool stop_ = false;
+  uint64_t next_ = 0;
+  std::map<uint64_t, std::shared_ptr<Ticket>> tickets_;
+  std::deque<uint64_t> queue_;
+  std::vector<std::shared_ptr<Ticket>> running_;
+};
+
+Engine* engine_for(hub_ctx* ctx, hipStream_t st) {
+  auto it = ctx->engines.find(st);
+  if (it != ctx->engines.end()) return it->second.get();
+  Engine* e = new Engine(ctx->pool.get(), st);
+  ctx->engines[st].reset(e);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hub_last_error(void) { return get_error(); }
+
+void hub_default_opts(hub_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->solver = HUB_CG_FP64;
+  o->max_iter = 20000;
+  o->restart_m = 10;
+  o->inner_max_iter = 4000;
+  o->tol = 1e-10;
+  o->inner_a = 5.0;
+  o->inner_floor = 1e-5;
+  o->use_x0 = 0;
+  o->check_every = 16;
+}
+
+hub_status hub_create(hub_ctx** ctx, int device, size_t hbm_budget_bytes) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  *ctx = nullptr;
+  int ndev = 0;
+  HUB_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(HUB_ERR_ARG, "no such device");
+  HUB_HIP(hipSetDevice(device), "hipSetDevice");
+  size_t freeb = 0, total = 0;
+  HUB_HIP(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+  hub_ctx* c = new hub_ctx;
+  c->device = device;
+  c->pool.reset(new Pool(device, hbm_budget_bytes ? hbm_budget_bytes : freeb / 4 * 3));
+  *ctx = c;
+  return HUB_OK;
+}
+
+hub_status hub_destroy(hub_ctx* ctx) {
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hipSetDevice(ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    ctx->server.reset();
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->engines.clear();
+  }
+  ctx->pool.reset();
+  delete ctx;
+  return HUB_OK;
+}
+
+static hub_status apply_common(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* x,
+                               hub_c128* y, int32_t batch, hipStream_t st, bool dag) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !x || !y) return fail(HUB_ERR_ARG, "NULL buffer");
+  if ((const void*)x == (const void*)y) return fail(HUB_ERR_ARG, "x and y must not overlap");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  HUB_HIP(launch_apply(g, phi, (const double2*)x, (double2*)y, batch, dag, st), "apply launch");
+  return HUB_OK;
+}
+
+hub_status hub_apply_M(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* x, hub_c128* y,
+                       int32_t batch, hipStream_t stream) {
+  return apply_common(ctx, lat, phi, x, y, batch, stream, false);
+}
+
+hub_status hub_apply_Mdag(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* x, hub_c128* y,
+                          int32_t batch, hipStream_t stream) {
+  return apply_common(ctx, lat, phi, x, y, batch, stream, true);
+}
+
+hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2,
+                            const hub_c128* x, hub_c128* y, int32_t batch, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !x || !y || !mu2) return fail(HUB_ERR_ARG, "NULL buffer");
+  if ((const void*)x == (const void*)y) return fail(HUB_ERR_ARG, "x and y must not overlap");
+  double m2[kMaxSys] = {0};
+  for (int b = 0; b < batch; ++b) {
+    if (!is_finite(mu2[b]) || mu2[b] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+    m2[b] = mu2[b];
+  }
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  void* u = ctx->pool->alloc((size_t)batch * g.n * 16, stream);
+  if (!u) return HUB_ERR_OOM;
+  hipError_t e = launch_apply(g, phi, (const double2*)x, (double2*)u, batch, true, stream);
+  if (e == hipSuccess)
+    e = launch_normal2(g, phi, m2, (const double2*)u, (const double2*)x, (double2*)y, batch, stream);
+  ctx->pool->release(u, stream);
+  if (e != hipSuccess) return hip_fail(e, "normal operator launch");
+  return HUB_OK;
+}
+
+hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2, int32_t batch,
+                     const hub_c128* b, hub_c128* x, const hub_solve_opts* opts, hub_solve_info* info,
+                     hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !b || !x || !mu2 || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  hub_solve_opts o;
+  hub_default_opts(&o);
+  if (opts) o = *opts;
+  if ((s = check_opts(o))) return s;
+  for (int k = 0; k < batch; ++k)
+    if (!is_finite(mu2[k]) || mu2[k] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  Engine* eng = engine_for(ctx, stream);
+  float* phi32 = nullptr;
+  if (o.solver == HUB_FGMRES_MIXED) {
+    phi32 = (float*)ctx->pool->alloc((size_t)g.n * 4, stream);
+    if (!phi32) return HUB_ERR_OOM;
+    HUB_HIP(launch_phi_to_f32(phi, phi32, g.n, stream), "phi conversion");
+  }
+  std::vector<System> sys((size_t)batch);
+  hub_status result = HUB_OK;
+  int added = 0;
+  for (int k = 0; k < batch; ++k) {
+    System& sy = sys[k];
+    sy.g = g;
+    sy.mu2 = mu2[k];
+    sy.phi = phi;
+    sy.phi32 = phi32;
+    sy.b = (const double2*)(b + (size_t)k * g.n);
+    sy.x = (double2*)(x + (size_t)k * g.n);
+    sy.opts = o;
+    if (!eng->add(&sy)) {
+      result = HUB_ERR_OOM;
+      break;
+    }
+    ++added;
+  }
+  if (result == HUB_OK) {
+    for (;;) {
+      hipError_t e = eng->step();
+      if (e != hipSuccess) {
+        result = hip_fail(e, "solve");
+        break;
+      }
+      bool all = true;
+      for (int k = 0; k < batch; ++k) all = all && sys[k].done;
+      if (all) break;
+    }
+  }
+  for (int k = 0; k < added; ++k) eng->remove(&sys[k]);
+  if (phi32) ctx->pool->release(phi32, stream);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (result != HUB_OK) return result;
+  if (e != hipSuccess) return hip_fail(e, "solve");
+  for (int k = 0; k < batch; ++k) {
+    info[k] = sys[k].info;
+    if (sys[k].status != HUB_OK && result == HUB_OK) result = sys[k].status;
+  }
+  if (result == HUB_ERR_NOCONV) set_error("iteration limit reached before the tolerance");
+  return result;
+}
+
+hub_status hub_force(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* eta,
+                     const hub_c128* xi, double scale, int32_t accumulate, double* dSdphi, int32_t batch,
+                     hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !eta || !dSdphi) return fail(HUB_ERR_ARG, "NULL buffer");
+  if (!is_finite(scale)) return fail(HUB_ERR_ARG, "scale must be finite");
+  if (accumulate != 0 && accumulate != 1) return fail(HUB_ERR_ARG, "accumulate must be 0 or 1");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  void* tmp = nullptr;
+  if (!xi) {
+    tmp = ctx->pool->alloc((size_t)batch * g.n * 16, stream);
+    if (!tmp) return HUB_ERR_OOM;
+    hipError_t e = launch_apply(g, phi, (const double2*)eta, (double2*)tmp, batch, true, stream);
+    if (e != hipSuccess) {
+      ctx->pool->release(tmp, stream);
+      return hip_fail(e, "xi launch");
+    }
+    xi = (const hub_c128*)tmp;
+  }
+  hipError_t e = launch_force(g, phi, (const double2*)eta, (const double2*)xi, scale, accumulate, dSdphi, batch,
+                              stream);
+  if (tmp) ctx->pool->release(tmp, stream);
+  if (e != hipSuccess) return hip_fail(e, "force launch");
+  return HUB_OK;
+}
+
+hub_status hub_action(hub_ctx* ctx, const hub_lattice* lat, const hub_c128* chi, const hub_c128* eta,
+                      int32_t batch, double* S, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!chi || !eta || !S) return fail(HUB_ERR_ARG, "NULL buffer");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  const int nt = ntiles_of(g.n);
+  const size_t part_bytes = (size_t)batch * nt * kMaxRed * sizeof(double);
+  char* ws = (char*)ctx->pool->alloc(part_bytes + 2 * 64 * sizeof(double), stream);
+  if (!ws) return HUB_ERR_OOM;
+  double* part = (double*)ws;
+  unsigned* counters = (unsigned*)(ws + part_bytes);
+  double* result = (double*)(ws + part_bytes + 64 * sizeof(double));
+  hipError_t e = hipMemsetAsync(counters, 0, 64 * sizeof(unsigned), stream);
+  if (e == hipSuccess)
+    e = launch_dot_re(g, (const double2*)chi, (const double2*)eta, batch, part, counters, result, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S, result, batch * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  ctx->pool->release(ws, stream);
+  if (e != hipSuccess) return hip_fail(e, "action");
+  return HUB_OK;
+}
+
+hub_status hub_submit(hub_ctx* ctx, const hub_request* req, uint64_t* ticket) {
+  set_error("");
+  if (!ctx || !req || !ticket) return fail(HUB_ERR_ARG, "NULL argument");
+  hub_status s = check_lattice(&req->lat);
+  if (s) return s;
+  if ((s = check_opts(req->opts))) return s;
+  if (!req->phi || !req->chi || !req->x_out) return fail(HUB_ERR_ARG, "NULL buffer");
+  if (!is_finite(req->mu2) || req->mu2 < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+  Server* srv;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    if (!ctx->server) ctx->server.reset(new Server(ctx));
+    srv = ctx->server.get();
+  }
+  return srv->submit(*req, ticket);
+}
+
+hub_status hub_poll(hub_ctx* ctx, uint64_t ticket, int32_t* done, hub_solve_info* info) {
+  set_error("");
+  if (!ctx || !done) return fail(HUB_ERR_ARG, "NULL argument");
+  Server* srv;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    srv = ctx->server.get();
+  }
+  if (!srv) return fail(HUB_ERR_NOTFOUND, "unknown ticket");
+  return srv->poll(ticket, done, info);
+}
+
+}  // extern "C"

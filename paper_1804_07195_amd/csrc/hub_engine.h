@@ -1,0 +1,130 @@
+// Host side of libhub: workspace pool and the batched solver engine.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hub.h"
+#include "hub_internal.h"
+
+namespace hub {
+
+// Thread-local error message behind hub_last_error().
+void set_error(const std::string& msg);
+const char* get_error();
+
+// Stream-ordered caching allocator of device memory, bounded by a byte budget.
+// A freed block is reused by the same stream at once and by other streams once
+// the work enqueued before its release has finished.
+class Pool {
+ public:
+  Pool(int device, size_t budget);
+  ~Pool();
+  // Returns nullptr (and sets the error) when the budget would be exceeded.
+  void* alloc(size_t bytes, hipStream_t st);
+  void release(void* p, hipStream_t st);
+  size_t budget() const { return budget_; }
+  size_t in_use() const;
+  size_t reserved() const;
+  // Bytes a request of this size takes from the budget (granularity rounding).
+  static size_t rounded(size_t bytes);
+
+ private:
+  struct Block {
+    void* p;
+    size_t bytes;
+    hipStream_t st;
+    hipEvent_t ev;
+  };
+  int device_;
+  size_t budget_;
+  size_t reserved_ = 0;  // bytes obtained from hipMalloc
+  size_t used_ = 0;      // bytes handed out
+  std::vector<Block> free_;
+  std::vector<std::pair<void*, size_t>> live_;
+  mutable std::mutex mu_;
+};
+
+// Host-side state of one linear system (M M^dagger + mu2) x = b.
+struct System {
+  // inputs
+  Geom g;
+  double mu2 = 0.0;
+  const double* phi = nullptr;
+  const float* phi32 = nullptr;
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  hub_solve_opts opts{};
+  // outputs
+  hub_solve_info info{};
+  hub_status status = HUB_OK;
+  bool done = false;
+  // engine bookkeeping
+  int slot = -1;
+  int phase = 0;
+  int post = 0;         // what follows the running single-precision CG
+  int j = 0;            // Arnoldi step
+  int cycles = 0;
+  int cg_total = 0;     // FP64 CG iterations over all restarts
+  double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
+  std::vector<std::complex<double>> H;  // (m+1) x m, column-major
+  std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload
+  std::vector<void*> owned;             // workspace blocks of this system
+  SysDesc desc{};
+  std::function<void(System*)> on_done; // serving: S, force and completion
+  void* user = nullptr;
+};
+
+// Drives any number (<= kMaxSys) of systems of any lattice sizes to convergence on
+// one stream.  Systems iterate together: every CG iteration is one pair of launches
+// over all systems currently iterating, whatever their phase or shape.
+class Engine {
+ public:
+  Engine(Pool* pool, hipStream_t st);
+  ~Engine();
+  // Allocate workspace and join; false (with the error set) if over budget or full.
+  bool add(System* s);
+  // Remove a finished system and return its workspace to the pool.
+  void remove(System* s);
+  // Advance every system: host-side phases, then one block of CG iterations.
+  // Returns the HIP error if any.
+  hipError_t step();
+  bool idle() const;
+  int count() const;
+  hipStream_t stream() const { return st_; }
+  // Workspace bytes a system of this shape and solver needs.
+  static size_t workspace_bytes(const Geom& g, const hub_solve_opts& o);
+  // Serving epilogue of a converged system: S = Re chi^dagger x (host), and
+  // dS/dphi into dSdphi (device, may be null).  Synchronises the stream.
+  hipError_t finalize(System* s, const double2* chi, double* dSdphi, double* S);
+
+ private:
+  hipError_t host_phase(System* s, bool& progressed);
+  hipError_t iterate(bool single);
+  hipError_t read_scal(const std::vector<System*>& v);
+  hipError_t upload_desc(System* s);
+  hipError_t upload_y(System* s, const std::vector<std::complex<double>>& y);
+  LaunchList one(System* s) const;
+  LaunchList list(const std::vector<System*>& v) const;
+  void finish(System* s, hub_status st);
+
+  Pool* pool_;
+  hipStream_t st_;
+  SysDesc* d_desc_ = nullptr;
+  Scal* d_scal_ = nullptr;
+  Scal* h_scal_ = nullptr;      // pinned mirror
+  unsigned* d_counter_ = nullptr;
+  std::vector<System*> slots_;
+};
+
+std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& H, int ldh, int k,
+                                                 double beta);
+
+Geom make_geom(const hub_lattice& lat);
+int ntiles_of(int n);
+
+}  // namespace hub

@@ -1,0 +1,650 @@
+// Host orchestration of the solves: workspace pool, the batched engine that runs
+// FP64 CG (Sec. 3) and the flexible GMRES with single-precision CG preconditioning
+// of Appendix A (Algorithm A.1) for many systems at once, and the small Hessenberg
+// least-squares problem of the FGMRES update.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "hub_engine.h"
+
+namespace hub {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_err;
+void set_error(const std::string& msg) { t_err = msg; }
+const char* get_error() { return t_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+Geom make_geom(const hub_lattice& lat) {
+  Geom g{};
+  g.L1 = lat.L1;
+  g.L2 = lat.L2;
+  g.Nt = lat.Nt;
+  g.P = lat.L1 * lat.L2;
+  g.n = 2 * g.P * lat.Nt;
+  g.dL2 = make_fastdiv((uint32_t)lat.L2);
+  g.dL1 = make_fastdiv((uint32_t)lat.L1);
+  g.kappa = lat.kappa_t;
+  g.ms = lat.ms_t;
+  return g;
+}
+
+int ntiles_of(int n) { return (n + kTile - 1) / kTile; }
+
+// ---------------------------------------------------------------------------
+// Pool
+// ---------------------------------------------------------------------------
+static constexpr size_t kGran = size_t(2) << 20;
+
+size_t Pool::rounded(size_t bytes) {
+  if (bytes >= kGran) return (bytes + kGran - 1) / kGran * kGran;
+  size_t r = 4096;
+  while (r < bytes) r <<= 1;
+  return r;
+}
+
+Pool::Pool(int device, size_t budget) : device_(device), budget_(budget) {}
+
+Pool::~Pool() {
+  hipSetDevice(device_);
+  for (auto& b : free_) {
+    hipEventSynchronize(b.ev);
+    hipEventDestroy(b.ev);
+    hipFree(b.p);
+  }
+  for (auto& l : live_) hipFree(l.first);
+}
+
+size_t Pool::in_use() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return used_;
+}
+
+size_t Pool::reserved() const {
+  std::lock_guard<std::mutex> lk(mu_);
+  return reserved_;
+}
+
+void* Pool::alloc(size_t bytes, hipStream_t st) {
+  const size_t sz = rounded(bytes == 0 ? 1 : bytes);
+  std::lock_guard<std::mutex> lk(mu_);
+  // reuse a cached block of the same size
+  for (size_t k = 0; k < free_.size(); ++k) {
+    Block& b = free_[k];
+    if (b.bytes != sz) continue;
+    if (b.st != st && hipEventQuery(b.ev) != hipSuccess) continue;
+    void* p = b.p;
+    hipEventDestroy(b.ev);
+    free_.erase(free_.begin() + (long)k);
+    live_.emplace_back(p, sz);
+    used_ += sz;
+    return p;
+  }
+  // release cached blocks until the new one fits
+  while (reserved_ + sz > budget_ && !free_.empty()) {
+    Block b = free_.back();
+    free_.pop_back();
+    hipEventSynchronize(b.ev);
+    hipEventDestroy(b.ev);
+    hipFree(b.p);
+    reserved_ -= b.bytes;
+  }
+  if (reserved_ + sz > budget_) {
+    set_error("workspace of " + std::to_string(sz) + " bytes exceeds the HBM budget (" +
+              std::to_string(reserved_) + " of " + std::to_string(budget_) + " bytes reserved)");
+    return nullptr;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sz) != hipSuccess) {
+    hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(sz) + " bytes failed");
+    return nullptr;
+  }
+  reserved_ += sz;
+  used_ += sz;
+  live_.emplace_back(p, sz);
+  return p;
+}
+
+void Pool::release(void* p, hipStream_t st) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
+  for (size_t k = 0; k < live_.size(); ++k) {
+    if (live_[k].first != p) continue;
+    Block b{p, live_[k].second, st, nullptr};
+    live_.erase(live_.begin() + (long)k);
+    used_ -= b.bytes;
+    hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    hipEventRecord(b.ev, st);
+    free_.push_back(b);
+    return;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// least squares  min | beta e_1 - H y |  for a (k+1) x k upper Hessenberg H
+// (Algorithm A.1 solves the normal equations by Cholesky; Givens rotations give
+// the same minimiser with better conditioning).
+// ---------------------------------------------------------------------------
+std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& Hin, int ldh, int k,
+                                                 double beta) {
+  using cd = std::complex<double>;
+  std::vector<cd> H(Hin);
+  std::vector<cd> gvec(k + 1, cd(0.0));
+  gvec[0] = beta;
+  auto at = [&](int i, int j) -> cd& { return H[(size_t)j * ldh + i]; };
+  for (int i = 0; i < k; ++i) {
+    const cd a = at(i, i), b = at(i + 1, i);
+    const double r = std::sqrt(std::norm(a) + std::norm(b));
+    if (r == 0.0) continue;
+    double c;
+    cd s;
+    if (std::abs(a) == 0.0) {
+      c = 0.0;
+      s = 1.0;
+    } else {
+      c = std::abs(a) / r;
+      s = (a / std::abs(a)) * std::conj(b) / r;
+    }
+    for (int j = i; j < k; ++j) {
+      const cd u = at(i, j), v = at(i + 1, j);
+      at(i, j) = c * u + s * v;
+      at(i + 1, j) = -std::conj(s) * u + c * v;
+    }
+    const cd u = gvec[i], v = gvec[i + 1];
+    gvec[i] = c * u + s * v;
+    gvec[i + 1] = -std::conj(s) * u + c * v;
+  }
+  std::vector<cd> y(k, cd(0.0));
+  for (int i = k - 1; i >= 0; --i) {
+    cd acc = gvec[i];
+    for (int j = i + 1; j < k; ++j) acc -= at(i, j) * y[j];
+    y[i] = at(i, i) == cd(0.0) ? cd(0.0) : acc / at(i, i);
+  }
+  return y;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+enum Phase : int {
+  PH_NEW = 0,
+  PH_CG_ITER,
+  PH_CG_CONFIRM,
+  PH_F_INNER,
+  PH_F_POST_INIT,
+  PH_F_ARNOLDI,
+  PH_F_POST_ARNOLDI,
+  PH_F_LSQ,
+  PH_DONE
+};
+
+#define HUB_TRY(expr)                        \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+
+Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSys, nullptr) {
+  hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys);
+  hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys);
+  hipMalloc(&d_counter_, sizeof(unsigned) * kMaxSys);
+  hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault);
+  hipMemsetAsync(d_counter_, 0, sizeof(unsigned) * kMaxSys, st_);
+  hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_);
+  std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
+}
+
+Engine::~Engine() {
+  hipStreamSynchronize(st_);
+  for (System* s : slots_)
+    if (s) remove(s);
+  hipFree(d_desc_);
+  hipFree(d_scal_);
+  hipFree(d_counter_);
+  hipHostFree(h_scal_);
+}
+
+bool Engine::idle() const {
+  for (System* s : slots_)
+    if (s && !s->done) return false;
+  return true;
+}
+
+int Engine::count() const {
+  int c = 0;
+  for (System* s : slots_) c += s != nullptr;
+  return c;
+}
+
+static bool is_fgmres(const hub_solve_opts& o) { return o.solver == HUB_FGMRES_MIXED; }
+
+size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
+  const size_t n = (size_t)g.n;
+  const size_t part = Pool::rounded((size_t)ntiles_of(g.n) * kMaxRed * sizeof(double));
+  if (!is_fgmres(o)) return 4 * Pool::rounded(n * 16) + part;
+  const int m = o.restart_m;
+  return (size_t)(m + 3) * Pool::rounded(n * 16) + (size_t)(m + 4) * Pool::rounded(n * 8) +
+         Pool::rounded(n * 4) + part;
+}
+
+bool Engine::add(System* s) {
+  int slot = -1;
+  for (int k = 0; k < kMaxSys; ++k)
+    if (!slots_[k]) {
+      slot = k;
+      break;
+    }
+  if (slot < 0) {
+    set_error("engine full");
+    return false;
+  }
+  const size_t n = (size_t)s->g.n;
+  SysDesc& d = s->desc;
+  std::memset(&d, 0, sizeof(d));
+  d.g = s->g;
+  d.mu2 = s->mu2;
+  d.phi = s->phi;
+  d.ntiles = ntiles_of(s->g.n);
+  d.sc = d_scal_ + slot;
+  d.counter = d_counter_ + slot;
+  auto get = [&](size_t bytes) -> void* {
+    void* p = pool_->alloc(bytes, st_);
+    if (p) s->owned.push_back(p);
+    return p;
+  };
+  bool ok = true;
+  d.part = (double*)get((size_t)d.ntiles * kMaxRed * sizeof(double));
+  ok = ok && d.part;
+  d.vec[S_B] = (void*)s->b;
+  d.vec[S_X] = (void*)s->x;
+  if (!is_fgmres(s->opts)) {
+    for (int k : {(int)S_R, (int)S_P0, (int)S_P0 + 1, (int)S_U}) {
+      d.vec[k] = get(n * 16);
+      ok = ok && d.vec[k];
+    }
+  } else {
+    const int m = s->opts.restart_m;
+    for (int k : {(int)S_R, (int)S_U}) {
+      d.vec[k] = get(n * 16);
+      ok = ok && d.vec[k];
+    }
+    for (int k = 0; k <= m && ok; ++k) {
+      d.vec[S_V0 + k] = get(n * 16);
+      ok = ok && d.vec[S_V0 + k];
+    }
+    for (int k : {(int)S_R32, (int)S_P32, (int)S_P32 + 1, (int)S_U32}) {
+      if (!ok) break;
+      d.vec[k] = get(n * 8);
+      ok = ok && d.vec[k];
+    }
+    for (int k = 0; k < m && ok; ++k) {
+      d.vec[S_Z0 + k] = get(n * 8);
+      ok = ok && d.vec[S_Z0 + k];
+    }
+    if (ok && !s->phi32) {
+      float* p32 = (float*)get(n * 4);
+      ok = ok && p32;
+      if (ok) {
+        if (launch_phi_to_f32(s->phi, p32, (int)n, st_) != hipSuccess) ok = false;
+        s->phi32 = p32;
+      }
+    }
+    d.phi32 = s->phi32;
+  }
+  if (!ok) {
+    for (void* p : s->owned) pool_->release(p, st_);
+    s->owned.clear();
+    return false;
+  }
+  s->slot = slot;
+  s->phase = PH_NEW;
+  s->done = false;
+  s->info = hub_solve_info{};
+  slots_[slot] = s;
+  if (upload_desc(s) != hipSuccess) {
+    slots_[slot] = nullptr;
+    for (void* p : s->owned) pool_->release(p, st_);
+    s->owned.clear();
+    set_error("descriptor upload failed");
+    return false;
+  }
+  return true;
+}
+
+void Engine::remove(System* s) {
+  if (s->slot >= 0 && slots_[s->slot] == s) slots_[s->slot] = nullptr;
+  for (void* p : s->owned) pool_->release(p, st_);
+  s->owned.clear();
+  s->slot = -1;
+}
+
+hipError_t Engine::upload_desc(System* s) {
+  return hipMemcpyAsync(d_desc_ + s->slot, &s->desc, sizeof(SysDesc), hipMemcpyHostToDevice, st_);
+}
+
+hipError_t Engine::upload_y(System* s, const std::vector<std::complex<double>>& y) {
+  static_assert(sizeof(std::complex<double>) == 2 * sizeof(double), "complex layout");
+  // The copy reads s->ybuf asynchronously; the next upload for this system happens
+  // only after a later synchronising read-back, so the buffer is not reused early.
+  s->ybuf = y;
+  return hipMemcpyAsync(&d_scal_[s->slot].y[0], s->ybuf.data(), sizeof(double) * 2 * y.size(),
+                        hipMemcpyHostToDevice, st_);
+}
+
+LaunchList Engine::one(System* s) const { return list(std::vector<System*>{s}); }
+
+LaunchList Engine::list(const std::vector<System*>& v) const {
+  LaunchList L;
+  std::memset(&L, 0, sizeof(L));
+  L.nsys = (int)v.size();
+  int acc = 0;
+  for (int k = 0; k < L.nsys; ++k) {
+    L.tile_begin[k] = acc;
+    L.sys[k] = v[k]->slot;
+    acc += v[k]->desc.ntiles;
+  }
+  L.tile_begin[L.nsys] = acc;
+  for (int k = L.nsys + 1; k <= kMaxSys; ++k) L.tile_begin[k] = acc;
+  L.total_tiles = acc;
+  return L;
+}
+
+hipError_t Engine::read_scal(const std::vector<System*>& v) {
+  int lo = kMaxSys, hi = -1;
+  for (System* s : v) {
+    lo = std::min(lo, s->slot);
+    hi = std::max(hi, s->slot);
+  }
+  if (hi < lo) return hipSuccess;
+  HUB_TRY(hipMemcpyAsync(h_scal_ + lo, d_scal_ + lo, sizeof(Scal) * (hi - lo + 1), hipMemcpyDeviceToHost, st_));
+  return hipStreamSynchronize(st_);
+}
+
+void Engine::finish(System* s, hub_status st) {
+  s->status = st;
+  s->phase = PH_DONE;
+  s->done = true;
+  s->info.converged = st == HUB_OK ? 1 : 0;
+}
+
+// One host-side transition of a system that is not iterating.
+hipError_t Engine::host_phase(System* s, bool& progressed) {
+  const hub_solve_opts& o = s->opts;
+  const double tol = o.tol;
+  switch (s->phase) {
+    case PH_NEW: {
+      progressed = true;
+      if (!is_fgmres(o)) {
+        if (!o.use_x0) {
+          LaunchList L = one(s);
+          L.pa[0] = 0.0;
+          L.pr[0] = tol * tol;
+          L.pi[0] = o.max_iter;
+          HUB_TRY(launch_cg_init_zero(d_desc_, L, st_));
+        } else {
+          LaunchList L = one(s);
+          HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
+          HUB_TRY(read_scal({s}));
+          s->bb = h_scal_[s->slot].red[0];
+          HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
+          L.pa[0] = tol * tol * s->bb;
+          L.pr[0] = 0.0;
+          L.pi[0] = o.max_iter;
+          HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+          s->info.applies++;
+        }
+        s->phase = PH_CG_ITER;
+        return hipSuccess;
+      }
+      // FGMRES: r = b (or b - A x0), |b|
+      LaunchList L = one(s);
+      if (!o.use_x0) {
+        L.pa[0] = 0.0;
+        L.pr[0] = 0.0;
+        L.pi[0] = 0;
+        HUB_TRY(launch_cg_init_zero(d_desc_, L, st_));
+        HUB_TRY(read_scal({s}));
+        s->bb = h_scal_[s->slot].red[0];
+        s->err = std::sqrt(s->bb);
+      } else {
+        HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
+        HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
+        HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 2, st_));
+        HUB_TRY(read_scal({s}));
+        s->bb = h_scal_[s->slot].red[0];
+        s->err = std::sqrt(h_scal_[s->slot].red[2]);
+        s->info.applies++;
+      }
+      s->bnorm = std::sqrt(s->bb);
+      if (s->bnorm == 0.0) {
+        // b = 0: x = 0 exactly
+        LaunchList Lz = one(s);
+        Lz.pi[0] = 0;
+        HUB_TRY(launch_cg_init_zero(d_desc_, Lz, st_));
+        s->info.true_rel_resid = 0.0;
+        finish(s, HUB_OK);
+        return hipSuccess;
+      }
+      if (s->err <= tol * s->bnorm) {
+        s->info.true_rel_resid = s->err / s->bnorm;
+        finish(s, HUB_OK);
+        return hipSuccess;
+      }
+      // initial single-precision solve on r (Algorithm A.1, first line)
+      const double tau = std::max(std::min(tol * o.inner_a * s->bnorm / s->err, 1.0), o.inner_floor);
+      L.pa[0] = 1.0;
+      L.pr[0] = tau * tau;
+      L.pi[0] = o.inner_max_iter;
+      L.pj[0] = S_Z0;
+      HUB_TRY(launch_prep_inner(d_desc_, L, S_R, -1, st_));
+      s->phase = PH_F_INNER;
+      s->post = PH_F_POST_INIT;
+      return hipSuccess;
+    }
+    case PH_CG_CONFIRM: {
+      progressed = true;
+      LaunchList L = one(s);
+      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
+      L.pa[0] = tol * tol * s->bb;
+      L.pr[0] = 0.0;
+      L.pi[0] = std::max(1, o.max_iter - s->cg_total);
+      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+      s->info.applies++;
+      HUB_TRY(read_scal({s}));
+      const double rr = h_scal_[s->slot].red[1];
+      s->info.true_rel_resid = s->bb > 0 ? std::sqrt(rr / s->bb) : 0.0;
+      if (s->info.true_rel_resid <= tol) {
+        finish(s, HUB_OK);
+      } else if (s->cg_total >= o.max_iter || !std::isfinite(rr)) {
+        finish(s, HUB_ERR_NOCONV);
+      } else {
+        s->info.outer_iters++;
+        s->phase = PH_CG_ITER;
+      }
+      return hipSuccess;
+    }
+    case PH_F_POST_INIT: {
+      progressed = true;
+      std::vector<std::complex<double>> y{std::complex<double>(1.0, 0.0)};
+      HUB_TRY(upload_y(s, y));
+      LaunchList L = one(s);
+      HUB_TRY(launch_xupdate(d_desc_, L, 1, !o.use_x0, st_));
+      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
+      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
+      s->info.applies++;
+      HUB_TRY(read_scal({s}));
+      s->err = std::sqrt(h_scal_[s->slot].red[0]);
+      s->info.true_rel_resid = s->err / s->bnorm;
+      if (s->err <= tol * s->bnorm) {
+        finish(s, HUB_OK);
+        return hipSuccess;
+      }
+      s->j = 0;
+      s->wnorm = s->err;
+      s->rnorm_cycle = s->err;
+      s->H.assign((size_t)(o.restart_m + 1) * o.restart_m, std::complex<double>(0.0));
+      s->phase = PH_F_ARNOLDI;
+      return hipSuccess;
+    }
+    case PH_F_ARNOLDI: {
+      progressed = true;
+      if (s->err < tol * s->bnorm || s->wnorm == 0.0 || !std::isfinite(s->wnorm)) {
+        s->phase = PH_F_LSQ;
+        return hipSuccess;
+      }
+      const int j = s->j;
+      const double ratio = tol * o.inner_a * s->bnorm / s->err;
+      LaunchList L = one(s);
+      L.pa[0] = 1.0 / s->wnorm;
+      L.pj[0] = S_Z0 + j;
+      if (ratio < 1.0) {
+        const double tau = std::max(ratio, o.inner_floor);
+        L.pr[0] = tau * tau;
+        L.pi[0] = o.inner_max_iter;
+        HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
+        s->phase = PH_F_INNER;
+        s->post = PH_F_POST_ARNOLDI;
+      } else {
+        L.pr[0] = 0.0;
+        L.pi[0] = 0;
+        HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
+        s->phase = PH_F_POST_ARNOLDI;
+      }
+      return hipSuccess;
+    }
+    case PH_F_POST_ARNOLDI: {
+      progressed = true;
+      const int j = s->j;
+      const int m = o.restart_m;
+      LaunchList L = one(s);
+      HUB_TRY(launch_mdag_slot(d_desc_, L, S_Z0 + j, true, st_));
+      HUB_TRY(launch_normal2_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
+      HUB_TRY(launch_multidot(d_desc_, L, S_R, S_V0, j + 1, 0, st_));
+      HUB_TRY(launch_cgs(d_desc_, L, S_R, S_V0, j + 1, 0, 2 * (j + 1), st_));
+      s->info.applies++;
+      HUB_TRY(read_scal({s}));
+      const Scal& sc = h_scal_[s->slot];
+      for (int i = 0; i <= j; ++i) s->H[(size_t)j * (m + 1) + i] = {sc.red[2 * i], sc.red[2 * i + 1]};
+      const double hn = std::sqrt(std::max(sc.red[2 * (j + 1)], 0.0));
+      s->H[(size_t)j * (m + 1) + j + 1] = hn;
+      s->wnorm = hn;
+      s->err *= hn;
+      s->j = j + 1;
+      s->phase = (s->j == m) ? PH_F_LSQ : PH_F_ARNOLDI;
+      return hipSuccess;
+    }
+    case PH_F_LSQ: {
+      progressed = true;
+      const int k = s->j;
+      const int m = o.restart_m;
+      LaunchList L = one(s);
+      if (k > 0) {
+        std::vector<std::complex<double>> y = hessenberg_lsq(s->H, m + 1, k, s->rnorm_cycle);
+        HUB_TRY(upload_y(s, y));
+        HUB_TRY(launch_xupdate(d_desc_, L, k, false, st_));
+      }
+      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
+      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
+      s->info.applies++;
+      s->cycles++;
+      s->info.outer_iters = s->cycles;
+      HUB_TRY(read_scal({s}));
+      s->err = std::sqrt(h_scal_[s->slot].red[0]);
+      s->info.true_rel_resid = s->err / s->bnorm;
+      if (s->err <= tol * s->bnorm) {
+        finish(s, HUB_OK);
+      } else if (s->cycles >= std::min(o.max_iter, 1000) || !std::isfinite(s->err) || k == 0) {
+        finish(s, HUB_ERR_NOCONV);
+      } else {
+        s->j = 0;
+        s->wnorm = s->err;
+        s->rnorm_cycle = s->err;
+        std::fill(s->H.begin(), s->H.end(), std::complex<double>(0.0));
+        s->phase = PH_F_ARNOLDI;
+      }
+      return hipSuccess;
+    }
+    default:
+      return hipSuccess;
+  }
+}
+
+// One block of CG iterations over every system that is iterating in the given precision.
+hipError_t Engine::iterate(bool single) {
+  std::vector<System*> v;
+  int k = 1 << 30;
+  for (System* s : slots_) {
+    if (!s || s->done) continue;
+    if ((single && s->phase == PH_F_INNER) || (!single && s->phase == PH_CG_ITER)) {
+      v.push_back(s);
+      k = std::min(k, std::max(1, s->opts.check_every));
+    }
+  }
+  if (v.empty()) return hipSuccess;
+  LaunchList L = list(v);
+  for (size_t q = 0; q < v.size(); ++q) L.pi[q] = single ? S_Z0 + v[q]->j : S_X;
+  // The solution slot of the initial single-precision solve is S_Z0 (j = 0 then).
+  for (int it = 0; it < k; ++it) HUB_TRY(launch_cg_iter(d_desc_, L, single, st_));
+  HUB_TRY(read_scal(v));
+  for (System* s : v) {
+    const Scal& sc = h_scal_[s->slot];
+    if (sc.active) continue;
+    if (single) {
+      s->info.inner_iters += sc.iters;
+      s->phase = s->post;
+    } else {
+      s->cg_total += sc.iters;
+      s->info.inner_iters = s->cg_total;
+      if (s->bb < 0) s->bb = sc.red[0];
+      s->phase = PH_CG_CONFIRM;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t Engine::step() {
+  bool progressed = true;
+  while (progressed) {
+    progressed = false;
+    for (System* s : slots_) {
+      if (!s || s->done) continue;
+      bool p = false;
+      HUB_TRY(host_phase(s, p));
+      progressed = progressed || p;
+      if (s->done && s->on_done) s->on_done(s);
+    }
+    // stop once every live system is iterating or done
+    bool all_wait = true;
+    for (System* s : slots_)
+      if (s && !s->done && s->phase != PH_F_INNER && s->phase != PH_CG_ITER) all_wait = false;
+    if (all_wait) break;
+  }
+  HUB_TRY(iterate(false));
+  HUB_TRY(iterate(true));
+  return hipSuccess;
+}
+
+}  // namespace hub
+
+namespace hub {
+
+hipError_t Engine::finalize(System* s, const double2* chi, double* dSdphi, double* S) {
+  const Geom& g = s->g;
+  double2* xi = (double2*)s->desc.vec[S_U];
+  HUB_TRY(launch_dot_re(g, chi, s->x, 1, s->desc.part, s->desc.counter, &d_scal_[s->slot].red[kMaxRed - 1], st_));
+  if (dSdphi) {
+    HUB_TRY(launch_apply(g, s->phi, s->x, xi, 1, true, st_));
+    HUB_TRY(launch_force(g, s->phi, s->x, xi, 1.0, 0, dSdphi, 1, st_));
+  }
+  HUB_TRY(read_scal({s}));
+  *S = h_scal_[s->slot].red[kMaxRed - 1];
+  return hipSuccess;
+}
+
+}  // namespace hub

@@ -1,0 +1,152 @@
+// Internal types shared by the HIP kernels and the host engine of libhub.
+// Not part of the public ABI (see include/hub.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hub {
+
+constexpr int kBlock = 256;                   // threads per workgroup (4 wave64)
+constexpr int kSitesPerThread = 4;            // sites handled by each thread
+constexpr int kTile = kBlock * kSitesPerThread;  // sites per workgroup tile
+constexpr int kMaxSys = 64;                   // systems per batched launch
+constexpr int kMaxRestart = 20;               // largest FGMRES restart length
+constexpr int kMaxRed = 2 * (kMaxRestart + 1) + 2;  // reduced doubles per tile (multi-dot)
+constexpr int kNumXcd = 8;                    // accelerator complex dies on MI355X
+constexpr int kMaxSlots = 64;                 // vector slots per system
+
+// Exact division by an invariant divisor for 0 <= n < 2^31 (Granlund-Montgomery):
+// q = (umulhi(n, m) + n) >> s with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f) {
+  uint32_t hi = (uint32_t)(((uint64_t)n * (uint64_t)f.m) >> 32);
+  return (hi + n) >> f.s;
+}
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+
+// Lattice geometry and couplings of one system, passed by value to kernels.
+struct Geom {
+  int L1, L2, Nt;
+  int P;   // L1*L2 sites per sublattice plane
+  int n;   // 2*P*Nt unknowns
+  int pad;
+  FastDiv dL2, dL1;
+  double kappa;  // kappa~ = delta*kappa
+  double ms;     // m~ = delta*m_s
+};
+
+// Per-system solver state written by kernels (device memory).
+struct Scal {
+  double rr;      // |r|^2 of the running CG
+  double alpha;
+  double beta;
+  double stop2;   // CG stops once |r|^2 <= stop2
+  double red[kMaxRed];               // results of the last generic reduction
+  double y[2 * kMaxRestart];         // FGMRES update coefficients (host-written)
+  int iters;      // CG iterations since the last setup
+  int maxit;
+  int active;     // 1 while CG iterations continue
+  int fresh;      // 1: next CG iteration starts with p = r
+};
+
+// Per-system descriptor (device memory, written by the host when a system joins).
+struct SysDesc {
+  Geom g;
+  double mu2;
+  const double* phi;     // float64 phi [n]
+  const float* phi32;    // float32 copy of phi [n] (single-precision path)
+  Scal* sc;
+  double* part;          // per-tile partial sums [ntiles][kMaxRed]
+  unsigned* counter;     // workgroups finished in the current reduction
+  int ntiles;
+  int pad;
+  void* vec[kMaxSlots];  // vector slots (type fixed by the slot's role)
+};
+
+// Systems of one batched launch: workgroup tiles are laid out system after system.
+struct LaunchList {
+  int nsys;
+  int total_tiles;
+  int tile_begin[kMaxSys + 1];
+  int sys[kMaxSys];     // index into the SysDesc array
+  double pa[kMaxSys];   // per-system kernel parameters (meaning set by the kernel)
+  double pr[kMaxSys];
+  int pi[kMaxSys];
+  int pj[kMaxSys];
+};
+
+// Vector slot roles.  FP64 slots hold double2 [n]; C64 slots hold float2 [n].
+enum Slot : int {
+  S_B = 0,     // right-hand side (FP64)
+  S_X = 1,     // solution (FP64)
+  S_R = 2,     // residual / Arnoldi w (FP64)
+  S_P0 = 3,    // CG direction, ping-pong pair S_P0, S_P0+1 (FP64)
+  S_U = 5,     // M^dagger p scratch (FP64)
+  S_V0 = 6,    // Arnoldi basis v_0 .. v_m (FP64), up to S_V0 + kMaxRestart
+  S_R32 = 40,  // single-precision CG residual (C64)
+  S_P32 = 41,  // single-precision CG direction pair S_P32, S_P32+1 (C64)
+  S_U32 = 43,  // single-precision M^dagger p scratch (C64)
+  S_Z0 = 44    // preconditioned directions z_0 .. z_{m-1} (C64), up to S_Z0 + kMaxRestart - 1
+};
+static_assert(S_V0 + kMaxRestart < S_R32, "slot layout");
+static_assert(S_Z0 + kMaxRestart <= kMaxSlots, "slot layout");
+
+// Reduction epilogue of the generic FP64 kernels.
+enum RedMode : int {
+  RED_NONE = 0,
+  RED_STORE = 1,     // sc->red[off..] = results
+  RED_CG_SETUP = 2   // CG (re)start: rr = result, stop2 = pa + pr*rr, iters 0, active, fresh
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (hub_kernels.hip).  All enqueue on `st` and return the HIP error.
+// ---------------------------------------------------------------------------
+hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch,
+                        bool dag, hipStream_t st);
+hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
+                          const double2* x, double2* y, int batch, hipStream_t st);
+hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi,
+                        double scale, int accumulate, double* out, int batch, hipStream_t st);
+hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
+                         unsigned* counters, double* result, hipStream_t st);
+hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st);
+
+// Batched solver kernels over the systems of a LaunchList (descriptors in `sys`).
+// FP64 or C64 CG iteration in two stages (see hub_kernels.hip).
+hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st);
+// u = M^dagger in; in is an FP64 slot or (in_c64) a C64 slot; u is S_U.
+hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st);
+// out = [b -] (M u + mu2 in), reduction of |out|^2 with the given epilogue.
+hipError_t launch_normal2_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b,
+                               int s_out, RedMode mode, int red_off, hipStream_t st);
+// x = 0, r = b, |r|^2 -> CG setup.
+hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, hipStream_t st);
+// red[off + 2i, 2i+1] = <v_i, w>, i < cnt.
+hipError_t launch_multidot(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int red_off,
+                           hipStream_t st);
+// w -= sum_i h_i v_i with h = red[h_off..]; |w|^2 -> red[red_off].
+hipError_t launch_cgs(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int h_off,
+                      int red_off, hipStream_t st);
+// v = pa*src (FP64, stored if s_v >= 0) and the single-precision CG start on it:
+// pi = maxit > 0: r32 = c64(v), z = 0, |r32|^2 -> setup with stop2 = pr*rr;
+// pi = 0 (no preconditioning): z = c64(v).  z is the slot pj.
+hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src, int s_v, hipStream_t st);
+// x = (set ? 0 : x) + sum_{i<cnt} y_i z_i (y from sc->y, z C64 slots from S_Z0).
+hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, int cnt, bool set, hipStream_t st);
+
+}  // namespace hub

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every entry
+point that include/hub.h declares, the ctypes structs match the header's layout,
+and argument errors are reported without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hub.h")
+LIB = os.path.join(ROOT, "paper_1804_07195_amd", "libhub.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hub_[a-z_A-Z]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1804_07195_amd.build_lib import build
+        build()
+    from paper_1804_07195_amd import binding
+    return binding.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_submit", "hub_poll",
+              "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_lists_every_symbol():
+    from paper_1804_07195_amd import binding
+    assert sorted(binding.SYMBOLS) == declared_functions()
+
+
+def test_struct_layouts_match_header():
+    from paper_1804_07195_amd import binding as b
+    assert ctypes.sizeof(b.HubLattice) == 32
+    assert b.HubLattice.kappa_t.offset == 16
+    assert ctypes.sizeof(b.HubSolveOpts) == 48
+    assert b.HubSolveOpts.tol.offset == 16 and b.HubSolveOpts.use_x0.offset == 40
+    assert ctypes.sizeof(b.HubSolveInfo) == 24
+    assert b.HubSolveInfo.true_rel_resid.offset == 16
+    assert b.HubRequest.opts.offset == 80
+
+
+def test_default_options(lib):
+    from paper_1804_07195_amd import binding as b
+    o = b.default_opts()
+    assert (o.solver, o.max_iter, o.restart_m, o.inner_max_iter) == (b.HUB_CG_FP64, 20000, 10, 4000)
+    assert (o.tol, o.inner_a, o.inner_floor, o.use_x0, o.check_every) == (1e-10, 5.0, 1e-5, 0, 16)
+
+
+def test_argument_errors_without_a_device(lib):
+    from paper_1804_07195_amd import binding as b
+    lat = b.lattice(3, 3, 8, 0.5)
+    # NULL context and NULL buffers are rejected before any HIP call
+    assert lib.hub_apply_M(None, ctypes.byref(lat), None, None, None, 1, None) == b.HUB_ERR_ARG
+    assert b"NULL" in lib.hub_last_error()
+    assert lib.hub_create(None, 0, 0) == b.HUB_ERR_ARG
+    info = b.HubSolveInfo()
+    assert lib.hub_solve(None, ctypes.byref(lat), None, None, 1, None, None, None, ctypes.byref(info), None) \
+        == b.HUB_ERR_ARG
+    done = ctypes.c_int32()
+    assert lib.hub_poll(None, ctypes.c_uint64(1), ctypes.byref(done), None) == b.HUB_ERR_ARG
+
+
+def test_create_without_device_reports_hip_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_1804_07195_amd import binding as b
+    h = ctypes.c_void_p()
+    assert lib.hub_create(ctypes.byref(h), 0, 0) == b.HUB_ERR_HIP
+    assert len(lib.hub_last_error()) > 0
