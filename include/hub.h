@@ -178,6 +178,26 @@ hub_status hub_submit(hub_ctx *ctx, const hub_request *req, uint64_t *ticket);
  * A finished request that missed its tolerance reports done with converged = 0. */
 hub_status hub_poll(hub_ctx *ctx, uint64_t ticket, int32_t *done, hub_solve_info *info);
 
+/* Measurement: time every launch of the solver's CG-iteration kernels with HIP
+ * events on the solve's stream.  Stats are per kernel: "cg1_f64", "cg2_f64" (the
+ * two kernels of an FP64 CG iteration) and "cg1_c64", "cg2_c64" (the same for the
+ * complex64 inner CG).  bytes accumulates the algorithmic bytes of every timed
+ * launch (per site: 72, 104, 36 and 52 bytes of distinct vector reads and writes,
+ * times the sites of the systems that iterated in that launch).  Timing adds an
+ * event record around each launch; it is off by default.
+ * hub_profile_enable resets the stats; enable = 0 turns timing off. */
+typedef struct {
+  char name[16];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} hub_kernel_stat;
+
+hub_status hub_profile_enable(hub_ctx *ctx, int32_t enable);
+/* Copy up to `max` stats (synchronous solves on every stream of the context) into
+ * out (host); *count receives the number written. */
+hub_status hub_profile_read(hub_ctx *ctx, hub_kernel_stat *out, int32_t max, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOC
                 5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
 
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
-           "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll"]
+           "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
+           "hub_profile_enable", "hub_profile_read"]
 
 
 class HubLattice(ctypes.Structure):
@@ -51,6 +52,11 @@ class HubRequest(ctypes.Structure):
     _fields_ = [("lat", HubLattice), ("mu2", ctypes.c_double), ("phi", ctypes.c_void_p), ("chi", ctypes.c_void_p),
                 ("x_out", ctypes.c_void_p), ("S_out", ctypes.POINTER(ctypes.c_double)),
                 ("dSdphi_out", ctypes.c_void_p), ("opts", HubSolveOpts)]
+
+
+class HubKernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class HubError(RuntimeError):
@@ -86,6 +92,8 @@ def load() -> ctypes.CDLL:
     L.hub_action.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.hub_submit.argtypes = [vp, ctypes.POINTER(HubRequest), ctypes.POINTER(ctypes.c_uint64)]
     L.hub_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(HubSolveInfo)]
+    L.hub_profile_enable.argtypes = [vp, i32]
+    L.hub_profile_read.argtypes = [vp, ctypes.POINTER(HubKernelStat), i32, ctypes.POINTER(i32)]
     for name in SYMBOLS:
         fn = getattr(L, name)
         if name not in ("hub_last_error", "hub_default_opts"):
@@ -276,6 +284,25 @@ def hub_poll(ctx: Context, pending) -> tuple:
     info = HubSolveInfo()
     _check(load().hub_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(info)))
     return bool(done.value), (info.as_dict() if done.value else None)
+
+
+def hub_profile_enable(ctx: Context, enable: bool = True) -> None:
+    """Time every CG-iteration kernel launch of later solves with HIP events (resets the stats)."""
+    _check(load().hub_profile_enable(ctx.handle, 1 if enable else 0))
+
+
+def hub_profile_read(ctx: Context) -> dict:
+    """{kernel: {launches, total_ms, bytes, avg_us, GBps}} of the timed launches."""
+    out = (HubKernelStat * 8)()
+    n = ctypes.c_int32()
+    _check(load().hub_profile_read(ctx.handle, out, 8, ctypes.byref(n)))
+    res = {}
+    for k in out[: n.value]:
+        d = {"launches": k.launches, "total_ms": k.total_ms, "bytes": k.bytes}
+        d["avg_us"] = 1e3 * k.total_ms / k.launches if k.launches else 0.0
+        d["GBps"] = k.bytes / (k.total_ms * 1e-3) / 1e9 if k.total_ms > 0 else 0.0
+        res[k.name.decode()] = d
+    return res
 
 
 class PseudofermionAction(torch.autograd.Function):

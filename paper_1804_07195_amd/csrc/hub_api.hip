@@ -88,6 +88,7 @@ struct hub_ctx {
   std::map<hipStream_t, std::unique_ptr<Engine>> engines;
   std::unique_ptr<Server> server;
   std::mutex server_mu;
+  bool profiling = false;
 };
 
 namespace {
@@ -236,6 +237,7 @@ Engine* engine_for(hub_ctx* ctx, hipStream_t st) {
   auto it = ctx->engines.find(st);
   if (it != ctx->engines.end()) return it->second.get();
   Engine* e = new Engine(ctx->pool.get(), st);
+  e->set_profiling(ctx->profiling);
   ctx->engines[st].reset(e);
   return e;
 }
@@ -454,15 +456,12 @@ hub_status hub_action(hub_ctx* ctx, const hub_lattice* lat, const hub_c128* chi,
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
   const int nt = ntiles_of(g.n);
-  const size_t part_bytes = (size_t)batch * nt * kMaxRed * sizeof(double);
-  char* ws = (char*)ctx->pool->alloc(part_bytes + 2 * 64 * sizeof(double), stream);
+  const size_t part_bytes = (size_t)batch * nt * sizeof(double);
+  char* ws = (char*)ctx->pool->alloc(part_bytes + 64 * sizeof(double), stream);
   if (!ws) return HUB_ERR_OOM;
   double* part = (double*)ws;
-  unsigned* counters = (unsigned*)(ws + part_bytes);
-  double* result = (double*)(ws + part_bytes + 64 * sizeof(double));
-  hipError_t e = hipMemsetAsync(counters, 0, 64 * sizeof(unsigned), stream);
-  if (e == hipSuccess)
-    e = launch_dot_re(g, (const double2*)chi, (const double2*)eta, batch, part, counters, result, stream);
+  double* result = (double*)(ws + part_bytes);
+  hipError_t e = launch_dot_re(g, (const double2*)chi, (const double2*)eta, batch, part, result, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(S, result, batch * sizeof(double), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   ctx->pool->release(ws, stream);
@@ -497,6 +496,39 @@ hub_status hub_poll(hub_ctx* ctx, uint64_t ticket, int32_t* done, hub_solve_info
   }
   if (!srv) return fail(HUB_ERR_NOTFOUND, "unknown ticket");
   return srv->poll(ticket, done, info);
+}
+
+hub_status hub_profile_enable(hub_ctx* ctx, int32_t enable) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->profiling = enable != 0;
+  for (auto& kv : ctx->engines) kv.second->set_profiling(ctx->profiling);
+  return HUB_OK;
+}
+
+hub_status hub_profile_read(hub_ctx* ctx, hub_kernel_stat* out, int32_t max, int32_t* count) {
+  set_error("");
+  if (!ctx || !out || !count) return fail(HUB_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  static const char* names[2][2] = {{"cg1_f64", "cg2_f64"}, {"cg1_c64", "cg2_c64"}};
+  int n = 0;
+  for (int sp = 0; sp < 2; ++sp)
+    for (int st = 0; st < 2; ++st) {
+      if (n >= max) break;
+      hub_kernel_stat k;
+      std::memset(&k, 0, sizeof(k));
+      std::strncpy(k.name, names[sp][st], sizeof(k.name) - 1);
+      for (auto& kv : ctx->engines) {
+        const Engine::KernelStat& e = kv.second->stat[sp][st];
+        k.launches += e.launches;
+        k.total_ms += e.ms;
+        k.bytes += e.bytes;
+      }
+      out[n++] = k;
+    }
+  *count = n;
+  return HUB_OK;
 }
 
 }  // extern "C"

@@ -70,6 +70,7 @@ struct System {
   int j = 0;            // Arnoldi step
   int cycles = 0;
   int cg_total = 0;     // FP64 CG iterations over all restarts
+  int enq = 0;          // CG iterations enqueued since the last CG setup
   double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
   std::vector<std::complex<double>> H;  // (m+1) x m, column-major
   std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload
@@ -98,6 +99,15 @@ class Engine {
   hipStream_t stream() const { return st_; }
   // Workspace bytes a system of this shape and solver needs.
   static size_t workspace_bytes(const Geom& g, const hub_solve_opts& o);
+  // Kernel timing of the CG stages (HIP events around every launch).
+  struct KernelStat {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+  };
+  void set_profiling(bool on);
+  // [single][stage-1]
+  KernelStat stat[2][2];
   // Serving epilogue of a converged system: S = Re chi^dagger x (host), and
   // dS/dphi into dSdphi (device, may be null).  Synchronises the stream.
   hipError_t finalize(System* s, const double2* chi, double* dSdphi, double* S);
@@ -117,8 +127,9 @@ class Engine {
   SysDesc* d_desc_ = nullptr;
   Scal* d_scal_ = nullptr;
   Scal* h_scal_ = nullptr;      // pinned mirror
-  unsigned* d_counter_ = nullptr;
   std::vector<System*> slots_;
+  bool profiling_ = false;
+  std::vector<hipEvent_t> events_;
 };
 
 std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& H, int ldh, int k,

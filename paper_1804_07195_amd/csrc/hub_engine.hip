@@ -193,20 +193,24 @@ enum Phase : int {
 Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSys, nullptr) {
   hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys);
   hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys);
-  hipMalloc(&d_counter_, sizeof(unsigned) * kMaxSys);
   hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault);
-  hipMemsetAsync(d_counter_, 0, sizeof(unsigned) * kMaxSys, st_);
   hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_);
   std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
 }
 
+void Engine::set_profiling(bool on) {
+  profiling_ = on;
+  for (auto& a : stat)
+    for (auto& b : a) b = KernelStat{};
+}
+
 Engine::~Engine() {
   hipStreamSynchronize(st_);
+  for (hipEvent_t e : events_) hipEventDestroy(e);
   for (System* s : slots_)
     if (s) remove(s);
   hipFree(d_desc_);
   hipFree(d_scal_);
-  hipFree(d_counter_);
   hipHostFree(h_scal_);
 }
 
@@ -226,7 +230,7 @@ static bool is_fgmres(const hub_solve_opts& o) { return o.solver == HUB_FGMRES_M
 
 size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
   const size_t n = (size_t)g.n;
-  const size_t part = Pool::rounded((size_t)ntiles_of(g.n) * kMaxRed * sizeof(double));
+  const size_t part = Pool::rounded((size_t)ntiles_of(g.n) * (kMaxRed + 2) * sizeof(double));
   if (!is_fgmres(o)) return 4 * Pool::rounded(n * 16) + part;
   const int m = o.restart_m;
   return (size_t)(m + 3) * Pool::rounded(n * 16) + (size_t)(m + 4) * Pool::rounded(n * 8) +
@@ -252,15 +256,18 @@ bool Engine::add(System* s) {
   d.phi = s->phi;
   d.ntiles = ntiles_of(s->g.n);
   d.sc = d_scal_ + slot;
-  d.counter = d_counter_ + slot;
   auto get = [&](size_t bytes) -> void* {
     void* p = pool_->alloc(bytes, st_);
     if (p) s->owned.push_back(p);
     return p;
   };
   bool ok = true;
-  d.part = (double*)get((size_t)d.ntiles * kMaxRed * sizeof(double));
+  d.part = (double*)get((size_t)d.ntiles * (kMaxRed + 2) * sizeof(double));
   ok = ok && d.part;
+  if (ok) {
+    d.part1 = d.part + (size_t)d.ntiles * kMaxRed;
+    d.part2 = d.part1 + d.ntiles;
+  }
   d.vec[S_B] = (void*)s->b;
   d.vec[S_X] = (void*)s->x;
   if (!is_fgmres(s->opts)) {
@@ -386,7 +393,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
           L.pa[0] = 0.0;
           L.pr[0] = tol * tol;
           L.pi[0] = o.max_iter;
-          HUB_TRY(launch_cg_init_zero(d_desc_, L, st_));
+          HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_CG_SETUP, st_));
         } else {
           LaunchList L = one(s);
           HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
@@ -399,16 +406,14 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
           HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
           s->info.applies++;
         }
+        s->enq = 0;
         s->phase = PH_CG_ITER;
         return hipSuccess;
       }
       // FGMRES: r = b (or b - A x0), |b|
       LaunchList L = one(s);
       if (!o.use_x0) {
-        L.pa[0] = 0.0;
-        L.pr[0] = 0.0;
-        L.pi[0] = 0;
-        HUB_TRY(launch_cg_init_zero(d_desc_, L, st_));
+        HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_STORE, st_));
         HUB_TRY(read_scal({s}));
         s->bb = h_scal_[s->slot].red[0];
         s->err = std::sqrt(s->bb);
@@ -425,8 +430,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       if (s->bnorm == 0.0) {
         // b = 0: x = 0 exactly
         LaunchList Lz = one(s);
-        Lz.pi[0] = 0;
-        HUB_TRY(launch_cg_init_zero(d_desc_, Lz, st_));
+        HUB_TRY(launch_cg_init_zero(d_desc_, Lz, RED_STORE, st_));
         s->info.true_rel_resid = 0.0;
         finish(s, HUB_OK);
         return hipSuccess;
@@ -443,6 +447,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       L.pi[0] = o.inner_max_iter;
       L.pj[0] = S_Z0;
       HUB_TRY(launch_prep_inner(d_desc_, L, S_R, -1, st_));
+      s->enq = 0;
       s->phase = PH_F_INNER;
       s->post = PH_F_POST_INIT;
       return hipSuccess;
@@ -465,6 +470,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
         finish(s, HUB_ERR_NOCONV);
       } else {
         s->info.outer_iters++;
+        s->enq = 0;
         s->phase = PH_CG_ITER;
       }
       return hipSuccess;
@@ -508,6 +514,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
         L.pr[0] = tau * tau;
         L.pi[0] = o.inner_max_iter;
         HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
+        s->enq = 0;
         s->phase = PH_F_INNER;
         s->post = PH_F_POST_ARNOLDI;
       } else {
@@ -590,8 +597,44 @@ hipError_t Engine::iterate(bool single) {
   LaunchList L = list(v);
   for (size_t q = 0; q < v.size(); ++q) L.pi[q] = single ? S_Z0 + v[q]->j : S_X;
   // The solution slot of the initial single-precision solve is S_Z0 (j = 0 then).
-  for (int it = 0; it < k; ++it) HUB_TRY(launch_cg_iter(d_desc_, L, single, st_));
+  std::vector<std::vector<int>> its;
+  if (profiling_) {
+    while ((int)events_.size() < 4 * k) {
+      hipEvent_t e;
+      HUB_TRY(hipEventCreate(&e));
+      events_.push_back(e);
+    }
+  }
+  for (int it = 0; it < k; ++it) {
+    for (size_t q = 0; q < v.size(); ++q) L.it[q] = v[q]->enq++;
+    if (!profiling_) {
+      HUB_TRY(launch_cg_iter(d_desc_, L, single, st_));
+      continue;
+    }
+    its.emplace_back(L.it, L.it + v.size());
+    HUB_TRY(launch_cg_stage(d_desc_, L, single, 1, st_, events_[4 * it], events_[4 * it + 1]));
+    HUB_TRY(launch_cg_stage(d_desc_, L, single, 2, st_, events_[4 * it + 2], events_[4 * it + 3]));
+  }
   HUB_TRY(read_scal(v));
+  if (profiling_) {
+    // A system did work in the launch of iteration `it` iff it < its final count
+    // (or it is still iterating).
+    for (int it = 0; it < k; ++it) {
+      double sites = 0.0;
+      for (size_t q = 0; q < v.size(); ++q) {
+        const Scal& sc = h_scal_[v[q]->slot];
+        if (sc.active || its[it][q] < sc.iters) sites += (double)v[q]->g.n;
+      }
+      for (int stage = 0; stage < 2; ++stage) {
+        float ms = 0.0f;
+        HUB_TRY(hipEventElapsedTime(&ms, events_[4 * it + 2 * stage], events_[4 * it + 2 * stage + 1]));
+        KernelStat& ks = stat[single ? 1 : 0][stage];
+        ks.launches++;
+        ks.ms += ms;
+        ks.bytes += sites * kCgBytes[single ? 1 : 0][stage];
+      }
+    }
+  }
   for (System* s : v) {
     const Scal& sc = h_scal_[s->slot];
     if (sc.active) continue;
@@ -637,7 +680,7 @@ namespace hub {
 hipError_t Engine::finalize(System* s, const double2* chi, double* dSdphi, double* S) {
   const Geom& g = s->g;
   double2* xi = (double2*)s->desc.vec[S_U];
-  HUB_TRY(launch_dot_re(g, chi, s->x, 1, s->desc.part, s->desc.counter, &d_scal_[s->slot].red[kMaxRed - 1], st_));
+  HUB_TRY(launch_dot_re(g, chi, s->x, 1, s->desc.part, &d_scal_[s->slot].red[kMaxRed - 1], st_));
   if (dSdphi) {
     HUB_TRY(launch_apply(g, s->phi, s->x, xi, 1, true, st_));
     HUB_TRY(launch_force(g, s->phi, s->x, xi, 1.0, 0, dSdphi, 1, st_));

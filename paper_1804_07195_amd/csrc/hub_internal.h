@@ -50,18 +50,19 @@ struct Geom {
   double ms;     // m~ = delta*m_s
 };
 
-// Per-system solver state written by kernels (device memory).
+// Per-system solver state (device memory).  Fields are written by the first
+// workgroup of a kernel and read by later kernels only, never by other
+// workgroups of the writing kernel (except `active`, whose readers take the same
+// decision whichever value they see).
 struct Scal {
-  double rr;      // |r|^2 of the running CG
-  double alpha;
-  double beta;
+  double rrv[2];  // |r_k|^2 of CG iteration k in rrv[k & 1]
   double stop2;   // CG stops once |r|^2 <= stop2
   double red[kMaxRed];               // results of the last generic reduction
   double y[2 * kMaxRestart];         // FGMRES update coefficients (host-written)
-  int iters;      // CG iterations since the last setup
+  int iters;      // CG iterations performed when the CG stopped
   int maxit;
   int active;     // 1 while CG iterations continue
-  int fresh;      // 1: next CG iteration starts with p = r
+  int pad;
 };
 
 // Per-system descriptor (device memory, written by the host when a system joins).
@@ -71,8 +72,9 @@ struct SysDesc {
   const double* phi;     // float64 phi [n]
   const float* phi32;    // float32 copy of phi [n] (single-precision path)
   Scal* sc;
-  double* part;          // per-tile partial sums [ntiles][kMaxRed]
-  unsigned* counter;     // workgroups finished in the current reduction
+  double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
+  double* part1;         // per-tile partials of CG stage 1 [ntiles]
+  double* part2;         // per-tile partials of CG stage 2 [ntiles]
   int ntiles;
   int pad;
   void* vec[kMaxSlots];  // vector slots (type fixed by the slot's role)
@@ -88,6 +90,7 @@ struct LaunchList {
   double pr[kMaxSys];
   int pi[kMaxSys];
   int pj[kMaxSys];
+  int it[kMaxSys];      // CG iteration index of each system in this launch
 };
 
 // Vector slot roles.  FP64 slots hold double2 [n]; C64 slots hold float2 [n].
@@ -106,11 +109,11 @@ enum Slot : int {
 static_assert(S_V0 + kMaxRestart < S_R32, "slot layout");
 static_assert(S_Z0 + kMaxRestart <= kMaxSlots, "slot layout");
 
-// Reduction epilogue of the generic FP64 kernels.
+// What a reduction finalisation does with its sums.
 enum RedMode : int {
   RED_NONE = 0,
   RED_STORE = 1,     // sc->red[off..] = results
-  RED_CG_SETUP = 2   // CG (re)start: rr = result, stop2 = pa + pr*rr, iters 0, active, fresh
+  RED_CG_SETUP = 2   // also CG (re)start: rrv[0] = result[0], stop2 = pa + pr*rr, iters 0, active
 };
 
 // ---------------------------------------------------------------------------
@@ -123,19 +126,28 @@ hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_hos
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi,
                         double scale, int accumulate, double* out, int batch, hipStream_t st);
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
-                         unsigned* counters, double* result, hipStream_t st);
+                         double* result, hipStream_t st);
 hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st);
 
 // Batched solver kernels over the systems of a LaunchList (descriptors in `sys`).
 // FP64 or C64 CG iteration in two stages (see hub_kernels.hip).
 hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st);
+// One stage (1 or 2) of the CG iteration.  With events, the launch records the
+// kernel's own start and end timestamps into them (hipExtLaunchKernel).
+hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
+                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Algorithmic bytes per site of each CG stage (reads + writes of distinct vectors).
+constexpr double kCgBytes[2][2] = {{72.0, 104.0}, {36.0, 52.0}};  // [single][stage-1]
 // u = M^dagger in; in is an FP64 slot or (in_c64) a C64 slot; u is S_U.
 hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st);
-// out = [b -] (M u + mu2 in), reduction of |out|^2 with the given epilogue.
+// Every reduction below leaves per-tile partials; a finalisation kernel (one
+// workgroup per system) sums them in a fixed order into sc->red[red_off..] and,
+// with RED_CG_SETUP, starts a CG on the result (pa, pr, pi of the launch list).
+// out = [b -] (M u + mu2 in), |out|^2 (mode RED_NONE: no reduction).
 hipError_t launch_normal2_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b,
                                int s_out, RedMode mode, int red_off, hipStream_t st);
-// x = 0, r = b, |r|^2 -> CG setup.
-hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, hipStream_t st);
+// x = 0, r = b, |b|^2 -> red[0]; with RED_CG_SETUP also the FP64 CG start.
+hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, RedMode mode, hipStream_t st);
 // red[off + 2i, 2i+1] = <v_i, w>, i < cnt.
 hipError_t launch_multidot(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int red_off,
                            hipStream_t st);

@@ -11,14 +11,29 @@
 //   the t +- 1 and i +- 1 neighbours of a tile are mostly in the same XCD's L2;
 // * the CG iteration is two kernels: (1) p = r + beta p on the fly, u = M^dagger p,
 //   <p, A p> = |u|^2 + mu^2 |p|^2; (2) q = M u + mu^2 p, x += alpha p, r -= alpha q,
-//   |r|^2.  Scalars alpha, beta and the convergence flag never leave the device;
-// * reductions are deterministic: wave64 butterfly, fixed LDS combine, one partial
-//   per tile, and the last workgroup of each system sums the partials in a fixed
-//   order.  Results depend only on the system's own shape, not on the batch.
+//   |r|^2.  Scalars alpha, beta and the convergence test never leave the device;
+// * reductions are deterministic and use no atomics: each workgroup stores one
+//   partial per tile (wave64 butterfly + fixed LDS combine), and every workgroup of
+//   the consuming kernel sums all partials of its system in the same fixed order,
+//   so all of them hold bit-identical alpha and beta.  A system's results depend
+//   only on its own shape, never on the other systems of the launch.
+#include <hip/hip_ext.h>
+
 #include "hub_internal.h"
 
 namespace hub {
 namespace {
+
+// Sites whose loads are issued together (per thread) in the stencil kernels.
+#ifndef HUB_SPT64
+#define HUB_SPT64 2
+#endif
+#ifndef HUB_SPT32
+#define HUB_SPT32 4
+#endif
+template <typename R> struct Spt;
+template <> struct Spt<double> { static constexpr int v = HUB_SPT64; };
+template <> struct Spt<float> { static constexpr int v = HUB_SPT32; };
 
 template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
@@ -40,6 +55,54 @@ template <typename C> __device__ __forceinline__ C cz() { C z; z.x = 0; z.y = 0;
 template <typename R, typename C>
 __device__ __forceinline__ R norm2(C a) { return a.x * a.x + a.y * a.y; }
 
+// Views of device vectors in the global address space.  Pointers read from a
+// descriptor are generic; accessing them through these views makes the compiler
+// emit global_* instead of flat_* memory instructions.
+#define HUB_GAS __attribute__((address_space(1)))
+typedef double hub_d2v __attribute__((ext_vector_type(2)));
+typedef float hub_f2v __attribute__((ext_vector_type(2)));
+template <typename C> struct Vec;
+template <> struct Vec<double2> {
+  HUB_GAS hub_d2v* p;
+  __device__ __forceinline__ explicit Vec(const void* q) : p((HUB_GAS hub_d2v*)q) {}
+  __device__ __forceinline__ double2 operator[](int k) const {
+    const hub_d2v v = p[k];
+    double2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+  }
+  __device__ __forceinline__ void set(int k, double2 a) const {
+    hub_d2v v;
+    v.x = a.x;
+    v.y = a.y;
+    p[k] = v;
+  }
+};
+template <> struct Vec<float2> {
+  HUB_GAS hub_f2v* p;
+  __device__ __forceinline__ explicit Vec(const void* q) : p((HUB_GAS hub_f2v*)q) {}
+  __device__ __forceinline__ float2 operator[](int k) const {
+    const hub_f2v v = p[k];
+    float2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+  }
+  __device__ __forceinline__ void set(int k, float2 a) const {
+    hub_f2v v;
+    v.x = a.x;
+    v.y = a.y;
+    p[k] = v;
+  }
+};
+template <typename T> struct Real {
+  HUB_GAS T* p;
+  __device__ __forceinline__ explicit Real(const void* q) : p((HUB_GAS T*)q) {}
+  __device__ __forceinline__ T operator[](int k) const { return p[k]; }
+  __device__ __forceinline__ void set(int k, T v) const { p[k] = v; }
+};
+
 // The stencil of M (DAG = false) or M^dagger (DAG = true) at site n.
 //   M,  A row: -x(n) + s (e^{ i phi(n)}  - m) x(t-1) - kappa sum_bonds x_B
 //   M,  B row: +x(n) - s (e^{-i phi(n)}  - m) x(t+1) - kappa sum_bonds x_A
@@ -47,9 +110,9 @@ __device__ __forceinline__ R norm2(C a) { return a.x * a.x + a.y * a.y; }
 //   M+, B row: +x(n) - s (e^{ i phi(tn)} - m) x(t-1) - kappa sum_bonds x_A
 // with s = -1 on a hop across the antiperiodic temporal boundary.  `ld(k)` returns
 // the input vector at site k; the own-site value is returned in `self`.
-template <typename R, bool DAG, typename PhiT, typename Load>
-__device__ __forceinline__ typename V2<R>::T stencil(const Geom& g, const PhiT* __restrict__ phi, int n,
-                                                     Load ld, typename V2<R>::T& self) {
+template <typename R, bool DAG, typename Phi, typename Load>
+__device__ __forceinline__ typename V2<R>::T stencil(const Geom& g, const Phi& phi, int n, Load ld,
+                                                     typename V2<R>::T& self) {
   using C = typename V2<R>::T;
   const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
   const int j = n - (int)q1 * g.L2;
@@ -101,6 +164,112 @@ __device__ __forceinline__ typename V2<R>::T stencil(const Geom& g, const PhiT* 
   return y;
 }
 
+// Index part of the stencil at site n (see `stencil`): own site, temporal
+// neighbour, three bonds, the phi index and the row's signs.
+struct SiteIdx {
+  int n, tn, h0, h1, h2, pn;
+  bool isA;
+  bool wrap;
+};
+
+template <bool DAG>
+__device__ __forceinline__ SiteIdx site_index(const Geom& g, int n) {
+  SiteIdx s;
+  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
+  const int j = n - (int)q1 * g.L2;
+  const uint32_t q2 = fdiv(q1, g.dL1);
+  const int i = (int)q1 - (int)q2 * g.L1;
+  s.isA = (q2 & 1u) == 0;
+  const int t = (int)(q2 >> 1);
+  const int P2 = 2 * g.P;
+  if (s.isA == DAG) {
+    s.wrap = t == g.Nt - 1;
+    s.tn = s.wrap ? n - (g.Nt - 1) * P2 : n + P2;
+  } else {
+    s.wrap = t == 0;
+    s.tn = s.wrap ? n + (g.Nt - 1) * P2 : n - P2;
+  }
+  if (s.isA) {
+    const int b = n + g.P;
+    s.h0 = b;
+    s.h1 = (i > 0) ? b - g.L2 : b + (g.L1 - 1) * g.L2;
+    s.h2 = (j > 0) ? b - 1 : b + g.L2 - 1;
+  } else {
+    const int a = n - g.P;
+    s.h0 = a;
+    s.h1 = (i < g.L1 - 1) ? a + g.L2 : a - (g.L1 - 1) * g.L2;
+    s.h2 = (j < g.L2 - 1) ? a + 1 : a - (g.L2 - 1);
+  }
+  s.n = n;
+  s.pn = DAG ? s.tn : n;
+  return s;
+}
+
+template <typename R, bool DAG, typename C>
+__device__ __forceinline__ C stencil_combine(const Geom& g, const SiteIdx& st, R ph, C xs, C xt, C x0, C x1,
+                                             C x2) {
+  R c, s;
+  phase_cs(ph, c, s);
+  const R sgn = st.wrap ? R(-1) : R(1);
+  const R es = (st.isA != DAG) ? s : -s;
+  const R cr = sgn * (c - (R)g.ms), ci = sgn * es;
+  const R tr = cr * xt.x - ci * xt.y, ti = cr * xt.y + ci * xt.x;
+  const R sig = st.isA ? R(-1) : R(1);
+  const R kap = (R)g.kappa;
+  C y;
+  y.x = sig * (xs.x - tr) - kap * (x0.x + x1.x + x2.x);
+  y.y = sig * (xs.y - ti) - kap * (x0.y + x1.y + x2.y);
+  return y;
+}
+
+// Apply the stencil to the kSitesPerThread sites of this thread in a tile, SPT
+// sites at a time: all index arithmetic first, then every load of the SPT sites
+// (stencil inputs, phi and the epilogue's own operands from `pre`), then the
+// arithmetic and `post(n, y, self, pre_value)`.  Issuing the loads of several sites
+// before the first wait keeps enough bytes in flight to cover HBM latency.  Lanes
+// past the end of the vector load a valid site and skip `post`.
+template <typename R, bool DAG, int SPT, typename Phi, typename Load, typename Pre, typename Post>
+__device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int base, Load ld, Pre pre,
+                                              Post post) {
+  using C = typename V2<R>::T;
+  using PV = decltype(pre(0));
+  static_assert(kSitesPerThread % SPT == 0, "SPT must divide kSitesPerThread");
+#pragma unroll
+  for (int r0 = 0; r0 < kSitesPerThread; r0 += SPT) {
+    SiteIdx st[SPT];
+    bool ok[SPT];
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      int n = base + (r0 + m) * kBlock;
+      ok[m] = n < g.n;
+      n = ok[m] ? n : g.n - 1;
+      st[m] = site_index<DAG>(g, n);
+    }
+    C xs[SPT], xt[SPT], x0[SPT], x1[SPT], x2[SPT];
+    R ph[SPT];
+    PV pv[SPT];
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      xs[m] = ld(st[m].n);
+      xt[m] = ld(st[m].tn);
+      x0[m] = ld(st[m].h0);
+      x1[m] = ld(st[m].h1);
+      x2[m] = ld(st[m].h2);
+      ph[m] = (R)phi[st[m].pn];
+      pv[m] = pre(st[m].n);
+    }
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      const C y = stencil_combine<R, DAG>(g, st[m], ph[m], xs[m], xt[m], x0[m], x1[m], x2[m]);
+      if (ok[m]) post(st[m].n, y, xs[m], pv[m]);
+    }
+  }
+}
+
+struct NoPre {
+  int dummy;
+};
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -119,31 +288,12 @@ __device__ __forceinline__ T block_sum(T v) {
   return (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
-// Publish this tile's `nv` block totals; the workgroup that finishes last sums all
-// tiles' partials in a fixed order into `out` (valid in every thread of that
-// workgroup) and returns true.  Resets the counter for the next reduction.
-__device__ bool finish_reduction(const double* vals, int nv, double* part, unsigned* counter, int ntiles,
-                                 int tile, double* out) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < nv; ++q)
-      __hip_atomic_store(&part[(size_t)tile * kMaxRed + q], vals[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(ntiles - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int q = 0; q < nv; ++q) {
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < ntiles; k += kBlock)
-      acc += __hip_atomic_load(&part[(size_t)k * kMaxRed + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double tot = block_sum(acc);
-    if (threadIdx.x == 0) out[q] = tot;
-  }
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  return true;
+// Sum of `cnt` partials spaced `stride` apart, fixed order, same value in every thread.
+__device__ __forceinline__ double sum_partials(const double* part, int cnt, int stride) {
+  const Real<double> p(part);
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < cnt; k += kBlock) acc += p[k * stride];
+  return block_sum(acc);
 }
 
 __device__ __forceinline__ int find_sys(const LaunchList& L, int lt) {
@@ -155,9 +305,16 @@ __device__ __forceinline__ int find_sys(const LaunchList& L, int lt) {
   return lo;
 }
 
-template <typename PhiT> __device__ __forceinline__ const PhiT* phi_of(const SysDesc* d);
-template <> __device__ __forceinline__ const double* phi_of<double>(const SysDesc* d) { return d->phi; }
-template <> __device__ __forceinline__ const float* phi_of<float>(const SysDesc* d) { return d->phi32; }
+template <typename PhiT> __device__ __forceinline__ Real<PhiT> phi_of(const SysDesc* d);
+template <> __device__ __forceinline__ Real<double> phi_of<double>(const SysDesc* d) { return Real<double>(d->phi); }
+template <> __device__ __forceinline__ Real<float> phi_of<float>(const SysDesc* d) { return Real<float>(d->phi32); }
+
+__device__ __forceinline__ int load_active(Scal* sc) {
+  return __hip_atomic_load(&sc->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_active(Scal* sc, int v) {
+  __hip_atomic_store(&sc->active, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Public operator kernels (shared phi, batch of vectors, no descriptors).
@@ -172,14 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   double2* __restrict__ yb = y + (size_t)b * g.n;
   const int base = tile * kTile + threadIdx.x;
   auto ld = [=](int k) { return xb[k]; };
-#pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
-    const int n = base + m * kBlock;
-    if (n < g.n) {
-      double2 self;
-      yb[n] = stencil<double, DAG>(g, phi, n, ld, self);
-    }
-  }
+  auto pre = [](int) { return NoPre{}; };
+  auto post = [=](int n, double2 v, double2, NoPre) { yb[n] = v; };
+  stencil_sites<double, DAG, Spt<double>::v>(g, phi, base, ld, pre, post);
 }
 
 struct Mu2Arr { double v[kMaxSys]; };
@@ -194,18 +346,13 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
   const double m2 = mu2.v[b];
   const int base = tile * kTile + threadIdx.x;
   auto ld = [=](int k) { return u[off + k]; };
-#pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
-    const int n = base + m * kBlock;
-    if (n < g.n) {
-      double2 self;
-      double2 q = stencil<double, false>(g, phi, n, ld, self);
-      const double2 xv = x[off + n];
-      q.x += m2 * xv.x;
-      q.y += m2 * xv.y;
-      y[off + n] = q;
-    }
-  }
+  auto pre = [=](int n) { return x[off + n]; };
+  auto post = [=](int n, double2 q, double2, double2 xv) {
+    q.x += m2 * xv.x;
+    q.y += m2 * xv.y;
+    y[off + n] = q;
+  };
+  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, pre, post);
 }
 
 // dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} xi(t-1)],
@@ -241,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restri
       sincos(phi[n], &s, &c);
       if (!isA) s = -s;
       const double2 e = eta[off + n], z = xi[off + tn];
-      // w = s*(c + i s) * z ; F = 2 Im(conj(e) * w)
+      // w = sgn (c + i s) z ; F = 2 Im(conj(e) w)
       const double wr = sgn * (c * z.x - s * z.y), wi = sgn * (c * z.y + s * z.x);
       const double F = 2.0 * (e.x * wi - e.y * wr);
       double* o = out + off + n;
@@ -250,10 +397,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restri
   }
 }
 
-// result[b] = Re sum conj(a_b) b_b, deterministic per b.
+// Per-tile partials of Re sum conj(a_b) b_b.
 __global__ __launch_bounds__(kBlock) void k_dot_re(Geom g, const double2* __restrict__ a,
-                                                   const double2* __restrict__ bb, int ntiles, double* part,
-                                                   unsigned* counters, double* result) {
+                                                   const double2* __restrict__ bb, int ntiles,
+                                                   double* __restrict__ part) {
   const int l = xcd_remap(blockIdx.x, gridDim.x);
   const int b = l / ntiles, tile = l - b * ntiles;
   const size_t off = (size_t)b * g.n;
@@ -267,11 +414,15 @@ __global__ __launch_bounds__(kBlock) void k_dot_re(Geom g, const double2* __rest
       acc += u.x * v.x + u.y * v.y;
     }
   }
-  double tot = block_sum(acc);
-  double out;
-  if (finish_reduction(&tot, 1, part + (size_t)b * ntiles * kMaxRed, counters + b, ntiles, tile, &out)) {
-    if (threadIdx.x == 0) result[b] = out;
-  }
+  const double tot = block_sum(acc);
+  if (threadIdx.x == 0) part[(size_t)b * ntiles + tile] = tot;
+}
+
+// result[b] = fixed-order sum of the partials of system b (one workgroup each).
+__global__ __launch_bounds__(kBlock) void k_dot_finish(const double* __restrict__ part, int ntiles,
+                                                       double* __restrict__ result) {
+  const double s = sum_partials(part + (size_t)blockIdx.x * ntiles, ntiles, 1);
+  if (threadIdx.x == 0) result[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_phi_to_f32(const double* __restrict__ phi, float* __restrict__ p32,
@@ -292,37 +443,46 @@ __global__ __launch_bounds__(kBlock) void k_phi_to_f32(const double* __restrict_
   const Geom g = d->g;                                 \
   const int base = tile * kTile + threadIdx.x;
 
-// CG stage 1: p_new = r + beta p_old (p_new = r on a fresh start), u = M^dagger p_new,
-// alpha = rr / (|u|^2 + mu^2 |p_new|^2).
+// CG stage 1 of iteration it = L.it[kk]:
+//   |r_it|^2 from the stage-2 partials of iteration it-1 (it > 0) and the stopping
+//   test; p_new = r + beta p_old with beta = |r_it|^2 / |r_{it-1}|^2 (p_new = r at
+//   it = 0), u = M^dagger p_new, partial of |u|^2 + mu^2 |p_new|^2 = <p, A p>.
 template <typename R, typename PhiT>
 __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
                                                 int sU) {
   using C = typename V2<R>::T;
   HUB_PROLOGUE
-  if (!sc->active) return;
-  const int it = sc->iters;
-  const bool fresh = sc->fresh != 0;
-  const R beta = (R)sc->beta;
-  const R mu2 = (R)d->mu2;
-  const C* __restrict__ r = (const C*)d->vec[sR];
-  const C* __restrict__ po = (const C*)d->vec[sP + (it & 1)];
-  C* __restrict__ pn = (C*)d->vec[sP + 1 - (it & 1)];
-  C* __restrict__ u = (C*)d->vec[sU];
-  const PhiT* __restrict__ phi = phi_of<PhiT>(d);
-  R acc = 0;
-  if (fresh) {
-    auto ld = [=](int k) { return r[k]; };
-#pragma unroll
-    for (int m = 0; m < kSitesPerThread; ++m) {
-      const int n = base + m * kBlock;
-      if (n < g.n) {
-        C p;
-        const C uu = stencil<R, true>(g, phi, n, ld, p);
-        pn[n] = p;
-        u[n] = uu;
-        acc += norm2<R>(uu) + mu2 * norm2<R>(p);
+  if (!load_active(sc)) return;
+  const int it = L.it[kk];
+  R beta = 0;
+  if (it > 0) {
+    const double rr = sum_partials(d->part2, d->ntiles, 1);
+    const double rr_prev = sc->rrv[(it - 1) & 1];
+    const bool first = (tile == 0 && threadIdx.x == 0);
+    if (!(rr > sc->stop2) || it >= sc->maxit) {
+      if (first) {
+        sc->rrv[it & 1] = rr;
+        sc->iters = it;
+        store_active(sc, 0);
       }
+      return;
     }
+    if (first) sc->rrv[it & 1] = rr;
+    beta = (R)(rr / rr_prev);
+  }
+  const R mu2 = (R)d->mu2;
+  const Vec<C> r(d->vec[sR]), po(d->vec[sP + (it & 1)]), pn(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]);
+  const Real<PhiT> phi = phi_of<PhiT>(d);
+  R acc = 0;
+  auto pre = [](int) { return NoPre{}; };
+  auto post = [&](int n, C uu, C p, NoPre) {
+    pn.set(n, p);
+    u.set(n, uu);
+    acc += norm2<R>(uu) + mu2 * norm2<R>(p);
+  };
+  if (it == 0) {
+    auto ld = [=](int k) { return r[k]; };
+    stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, pre, post);
   } else {
     auto ld = [=](int k) {
       const C a = r[k], b = po[k];
@@ -331,73 +491,48 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
       o.y = a.y + beta * b.y;
       return o;
     };
-#pragma unroll
-    for (int m = 0; m < kSitesPerThread; ++m) {
-      const int n = base + m * kBlock;
-      if (n < g.n) {
-        C p;
-        const C uu = stencil<R, true>(g, phi, n, ld, p);
-        pn[n] = p;
-        u[n] = uu;
-        acc += norm2<R>(uu) + mu2 * norm2<R>(p);
-      }
-    }
+    stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, pre, post);
   }
-  double tot = (double)block_sum(acc);
-  double pq;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &pq)) {
-    if (threadIdx.x == 0) sc->alpha = sc->rr / pq;
-  }
+  const double tot = (double)block_sum(acc);
+  if (threadIdx.x == 0) Real<double>(d->part1).set(tile, tot);
 }
 
-// CG stage 2: q = M u + mu^2 p, x += alpha p, r -= alpha q; beta = |r|^2_new / |r|^2
-// and the convergence flag.  The solution slot of system k is L.pi[k].
+// CG stage 2 of iteration it: alpha = |r_it|^2 / <p, A p> (stage-1 partials),
+// q = M u + mu^2 p, x += alpha p, r -= alpha q, partial of |r_{it+1}|^2.
+// The solution slot of system k is L.pi[k].
 template <typename R, typename PhiT>
 __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
                                                 int sU) {
   using C = typename V2<R>::T;
   HUB_PROLOGUE
-  if (!sc->active) return;
-  const int it = sc->iters;
-  const R alpha = (R)sc->alpha;
+  if (!load_active(sc)) return;
+  const int it = L.it[kk];
+  const double pq = sum_partials(d->part1, d->ntiles, 1);
+  const R alpha = (R)(sc->rrv[it & 1] / pq);
   const R mu2 = (R)d->mu2;
-  const C* __restrict__ p = (const C*)d->vec[sP + 1 - (it & 1)];
-  const C* __restrict__ u = (const C*)d->vec[sU];
-  C* __restrict__ x = (C*)d->vec[L.pi[kk]];
-  C* __restrict__ r = (C*)d->vec[sR];
-  const PhiT* __restrict__ phi = phi_of<PhiT>(d);
+  const Vec<C> p(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]), x(d->vec[L.pi[kk]]), r(d->vec[sR]);
+  const Real<PhiT> phi = phi_of<PhiT>(d);
   auto ld = [=](int k) { return u[k]; };
+  struct Own {
+    C p, x, r;
+  };
+  auto pre = [=](int n) { return Own{p[n], x[n], r[n]}; };
   R acc = 0;
-#pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
-    const int n = base + m * kBlock;
-    if (n < g.n) {
-      C self;
-      C q = stencil<R, false>(g, phi, n, ld, self);
-      const C pv = p[n];
-      q.x += mu2 * pv.x;
-      q.y += mu2 * pv.y;
-      C xv = x[n], rv = r[n];
-      xv.x += alpha * pv.x;
-      xv.y += alpha * pv.y;
-      rv.x -= alpha * q.x;
-      rv.y -= alpha * q.y;
-      x[n] = xv;
-      r[n] = rv;
-      acc += norm2<R>(rv);
-    }
-  }
-  double tot = (double)block_sum(acc);
-  double rr_new;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &rr_new)) {
-    if (threadIdx.x == 0) {
-      sc->beta = rr_new / sc->rr;
-      sc->rr = rr_new;
-      sc->iters = it + 1;
-      sc->fresh = 0;
-      if (!(rr_new > sc->stop2) || it + 1 >= sc->maxit) sc->active = 0;
-    }
-  }
+  auto post = [&](int n, C q, C, Own o) {
+    q.x += mu2 * o.p.x;
+    q.y += mu2 * o.p.y;
+    C xv = o.x, rv = o.r;
+    xv.x += alpha * o.p.x;
+    xv.y += alpha * o.p.y;
+    rv.x -= alpha * q.x;
+    rv.y -= alpha * q.y;
+    x.set(n, xv);
+    r.set(n, rv);
+    acc += norm2<R>(rv);
+  };
+  stencil_sites<R, false, Spt<R>::v>(g, phi, base, ld, pre, post);
+  const double tot = (double)block_sum(acc);
+  if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }
 
 template <typename Tin> __device__ __forceinline__ double2 to_c128(Tin v);
@@ -414,110 +549,91 @@ template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_mdag_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in) {
   HUB_PROLOGUE
   (void)sc;
-  const Tin* __restrict__ in = (const Tin*)d->vec[s_in];
-  double2* __restrict__ u = (double2*)d->vec[S_U];
+  const Vec<Tin> in(d->vec[s_in]);
+  const Vec<double2> u(d->vec[S_U]);
+  const Real<double> phi = phi_of<double>(d);
   auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
-#pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
-    const int n = base + m * kBlock;
-    if (n < g.n) {
-      double2 self;
-      u[n] = stencil<double, true>(g, d->phi, n, ld, self);
-    }
+  auto pre = [](int) { return NoPre{}; };
+  auto post = [=](int n, double2 v, double2, NoPre) { u.set(n, v); };
+  stencil_sites<double, true, Spt<double>::v>(g, phi, base, ld, pre, post);
+}
+
+__device__ __forceinline__ void store_partials(const SysDesc* d, int tile, const double* vals, int nv) {
+  if (threadIdx.x == 0) {
+    const Real<double> p(d->part + (size_t)tile * kMaxRed);
+    for (int q = 0; q < nv; ++q) p.set(q, vals[q]);
   }
 }
 
-__device__ __forceinline__ void cg_setup(Scal* sc, double rr, double pa, double pr, int maxit) {
-  sc->rr = rr;
-  sc->stop2 = pa + pr * rr;
-  sc->iters = 0;
-  sc->maxit = maxit;
-  sc->fresh = 1;
-  sc->active = (rr > sc->stop2) ? 1 : 0;
-}
-
-// out = [b -] (M u + mu^2 in), |out|^2 reduced with the given epilogue.
+// out = [b -] (M u + mu^2 in), partial of |out|^2 unless mode == RED_NONE.
 template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_normal2_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in,
-                                                         int s_b, int s_out, int mode, int red_off) {
+                                                         int s_b, int s_out, int mode) {
   HUB_PROLOGUE
-  const Tin* __restrict__ in = (const Tin*)d->vec[s_in];
-  const double2* __restrict__ bv = s_b >= 0 ? (const double2*)d->vec[s_b] : nullptr;
-  const double2* __restrict__ u = (const double2*)d->vec[S_U];
-  double2* __restrict__ out = (double2*)d->vec[s_out];
+  (void)sc;
+  const Vec<Tin> in(d->vec[s_in]);
+  const bool has_b = s_b >= 0;
+  const Vec<double2> bv(has_b ? d->vec[s_b] : nullptr), u(d->vec[S_U]), out(d->vec[s_out]);
+  const Real<double> phi = phi_of<double>(d);
   const double mu2 = d->mu2;
   auto ld = [=](int k) { return u[k]; };
+  struct Own {
+    double2 x, b;
+  };
+  auto pre = [=](int n) { return Own{to_c128<Tin>(in[n]), has_b ? bv[n] : cz<double2>()}; };
   double acc = 0.0;
-#pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
-    const int n = base + m * kBlock;
-    if (n < g.n) {
-      double2 self;
-      double2 q = stencil<double, false>(g, d->phi, n, ld, self);
-      const double2 xv = to_c128<Tin>(in[n]);
-      q.x += mu2 * xv.x;
-      q.y += mu2 * xv.y;
-      if (bv) {
-        const double2 b = bv[n];
-        q.x = b.x - q.x;
-        q.y = b.y - q.y;
-      }
-      out[n] = q;
-      acc += norm2<double>(q);
+  auto post = [&](int n, double2 q, double2, Own o) {
+    q.x += mu2 * o.x.x;
+    q.y += mu2 * o.x.y;
+    if (has_b) {
+      q.x = o.b.x - q.x;
+      q.y = o.b.y - q.y;
     }
-  }
+    out.set(n, q);
+    acc += norm2<double>(q);
+  };
+  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, pre, post);
   if (mode == RED_NONE) return;
-  double tot = block_sum(acc);
-  double res;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &res)) {
-    if (threadIdx.x == 0) {
-      sc->red[red_off] = res;
-      if (mode == RED_CG_SETUP) cg_setup(sc, res, L.pa[kk], L.pr[kk], L.pi[kk]);
-    }
-  }
+  const double tot = block_sum(acc);
+  store_partials(d, tile, &tot, 1);
 }
 
-// x = 0, r = b; |b|^2 -> red[0] and the FP64 CG setup.
+// x = 0, r = b; partial of |b|^2.
 __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restrict__ sys, LaunchList L) {
   HUB_PROLOGUE
-  const double2* __restrict__ b = (const double2*)d->vec[S_B];
-  double2* __restrict__ x = (double2*)d->vec[S_X];
-  double2* __restrict__ r = (double2*)d->vec[S_R];
+  (void)sc;
+  const Vec<double2> b(d->vec[S_B]), x(d->vec[S_X]), r(d->vec[S_R]);
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
       const double2 v = b[n];
-      r[n] = v;
-      x[n] = cz<double2>();
+      r.set(n, v);
+      x.set(n, cz<double2>());
       acc += norm2<double>(v);
     }
   }
-  double tot = block_sum(acc);
-  double res;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &res)) {
-    if (threadIdx.x == 0) {
-      sc->red[0] = res;
-      cg_setup(sc, res, L.pa[kk], L.pr[kk], L.pi[kk]);
-    }
-  }
+  const double tot = block_sum(acc);
+  store_partials(d, tile, &tot, 1);
 }
 
-// red[off + 2i], red[off + 2i + 1] = <v_i, w> = sum conj(v_i) w, i < cnt.
+// partials of <v_i, w> = sum conj(v_i) w, i < cnt (re, im interleaved).
 __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__ sys, LaunchList L, int s_w,
-                                                     int s_v0, int cnt, int red_off) {
+                                                     int s_v0, int cnt) {
   HUB_PROLOGUE
-  const double2* __restrict__ w = (const double2*)d->vec[s_w];
+  (void)sc;
+  const Vec<double2> w(d->vec[s_w]);
   double2 wv[kSitesPerThread];
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
-    wv[m] = n < g.n ? w[n] : cz<double2>();
+    wv[m] = cz<double2>();
+    if (n < g.n) wv[m] = w[n];
   }
   __shared__ double tot[kMaxRed];
   for (int q = 0; q < cnt; ++q) {
-    const double2* __restrict__ v = (const double2*)d->vec[s_v0 + q];
+    const Vec<double2> v(d->vec[s_v0 + q]);
     double ar = 0.0, ai = 0.0;
 #pragma unroll
     for (int m = 0; m < kSitesPerThread; ++m) {
@@ -536,27 +652,24 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__
     }
   }
   __syncthreads();
-  __shared__ double res[kMaxRed];
-  if (finish_reduction(tot, 2 * cnt, d->part, d->counter, d->ntiles, tile, res)) {
-    if (threadIdx.x == 0)
-      for (int q = 0; q < 2 * cnt; ++q) sc->red[red_off + q] = res[q];
-  }
+  store_partials(d, tile, tot, 2 * cnt);
 }
 
-// w -= sum_i h_i v_i, h_i = red[h_off + 2i] + i red[h_off + 2i + 1]; |w|^2 -> red[red_off].
+// w -= sum_i h_i v_i, h_i = red[h_off + 2i] + i red[h_off + 2i + 1]; partial of |w|^2.
 __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys, LaunchList L, int s_w, int s_v0,
-                                                int cnt, int h_off, int red_off) {
+                                                int cnt, int h_off) {
   HUB_PROLOGUE
-  double2* __restrict__ w = (double2*)d->vec[s_w];
+  const Vec<double2> w(d->vec[s_w]);
   double2 wv[kSitesPerThread];
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
-    wv[m] = n < g.n ? w[n] : cz<double2>();
+    wv[m] = cz<double2>();
+    if (n < g.n) wv[m] = w[n];
   }
   for (int q = 0; q < cnt; ++q) {
     const double hr = sc->red[h_off + 2 * q], hi = sc->red[h_off + 2 * q + 1];
-    const double2* __restrict__ v = (const double2*)d->vec[s_v0 + q];
+    const Vec<double2> v(d->vec[s_v0 + q]);
 #pragma unroll
     for (int m = 0; m < kSitesPerThread; ++m) {
       const int n = base + m * kBlock;
@@ -572,30 +685,27 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
-      w[n] = wv[m];
+      w.set(n, wv[m]);
       acc += norm2<double>(wv[m]);
     }
   }
-  double tot = block_sum(acc);
-  double res;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &res)) {
-    if (threadIdx.x == 0) sc->red[red_off] = res;
-  }
+  const double tot = block_sum(acc);
+  store_partials(d, tile, &tot, 1);
 }
 
 // v = pa*src (FP64, stored to s_v if s_v >= 0).  With pi = maxit > 0 the
-// single-precision CG starts on v: r32 = c64(v), z = 0, rr = |r32|^2 (FP32 sums),
-// stop2 = pr*rr.  With pi = 0 there is no preconditioning: z = c64(v).  The z slot
-// of system k is pj[k].
+// single-precision CG starts on v: r32 = c64(v), z = 0, partial of |r32|^2 (FP32
+// sums).  With pi = 0 there is no preconditioning: z = c64(v).  The z slot of
+// system k is pj[k].
 __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict__ sys, LaunchList L, int s_src,
                                                        int s_v) {
   HUB_PROLOGUE
+  (void)sc;
   const double scale = L.pa[kk];
   const int maxit = L.pi[kk];
-  const double2* __restrict__ src = (const double2*)d->vec[s_src];
-  double2* __restrict__ v = s_v >= 0 ? (double2*)d->vec[s_v] : nullptr;
-  float2* __restrict__ z = (float2*)d->vec[L.pj[kk]];
-  float2* __restrict__ r32 = (float2*)d->vec[S_R32];
+  const bool store_v = s_v >= 0;
+  const Vec<double2> src(d->vec[s_src]), v(store_v ? d->vec[s_v] : nullptr);
+  const Vec<float2> z(d->vec[L.pj[kk]]), r32(d->vec[S_R32]);
   float acc = 0.0f;
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
@@ -604,24 +714,45 @@ __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict
       double2 a = src[n];
       a.x *= scale;
       a.y *= scale;
-      if (v) v[n] = a;
+      if (store_v) v.set(n, a);
       float2 a32;
       a32.x = (float)a.x;
       a32.y = (float)a.y;
       if (maxit > 0) {
-        r32[n] = a32;
-        z[n] = cz<float2>();
+        r32.set(n, a32);
+        z.set(n, cz<float2>());
         acc += norm2<float>(a32);
       } else {
-        z[n] = a32;
+        z.set(n, a32);
       }
     }
   }
   if (maxit <= 0) return;
-  double tot = (double)block_sum(acc);
-  double res;
-  if (finish_reduction(&tot, 1, d->part, d->counter, d->ntiles, tile, &res)) {
-    if (threadIdx.x == 0) cg_setup(sc, res, 0.0, L.pr[kk], maxit);
+  const double tot = (double)block_sum(acc);
+  store_partials(d, tile, &tot, 1);
+}
+
+// One workgroup per system: sum the generic partials (nv values) in a fixed order
+// into red[red_off..]; with RED_CG_SETUP start a CG on rr = result[0]:
+// stop2 = pa + pr*rr, maxit = pi, iters 0, active iff rr > stop2.
+__global__ __launch_bounds__(kBlock) void k_finish(const SysDesc* __restrict__ sys, LaunchList L, int nv,
+                                                   int red_off, int mode) {
+  const int kk = blockIdx.x;
+  const SysDesc* __restrict__ d = sys + L.sys[kk];
+  Scal* sc = d->sc;
+  for (int q = 0; q < nv; ++q) {
+    const double s = sum_partials(d->part + q, d->ntiles, kMaxRed);
+    if (threadIdx.x == 0) {
+      sc->red[red_off + q] = s;
+      if (q == 0 && mode == RED_CG_SETUP) {
+        const double stop2 = L.pa[kk] + L.pr[kk] * s;
+        sc->rrv[0] = s;
+        sc->stop2 = stop2;
+        sc->maxit = L.pi[kk];
+        sc->iters = 0;
+        store_active(sc, s > stop2 ? 1 : 0);
+      }
+    }
   }
 }
 
@@ -629,16 +760,17 @@ __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict
 __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ sys, LaunchList L, int cnt,
                                                     int set) {
   HUB_PROLOGUE
-  double2* __restrict__ x = (double2*)d->vec[S_X];
+  const Vec<double2> x(d->vec[S_X]);
   double2 xv[kSitesPerThread];
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
-    xv[m] = (n < g.n && !set) ? x[n] : cz<double2>();
+    xv[m] = cz<double2>();
+    if (n < g.n && !set) xv[m] = x[n];
   }
   for (int q = 0; q < cnt; ++q) {
     const double yr = sc->y[2 * q], yi = sc->y[2 * q + 1];
-    const float2* __restrict__ z = (const float2*)d->vec[S_Z0 + q];
+    const Vec<float2> z(d->vec[S_Z0 + q]);
 #pragma unroll
     for (int m = 0; m < kSitesPerThread; ++m) {
       const int n = base + m * kBlock;
@@ -653,18 +785,15 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
 #pragma unroll
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
-    if (n < g.n) x[n] = xv[m];
+    if (n < g.n) x.set(n, xv[m]);
   }
 }
 
 }  // namespace
-}  // namespace hub
 
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-namespace hub {
-
 static inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }
 
 hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
@@ -695,9 +824,10 @@ hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, co
 }
 
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
-                         unsigned* counters, double* result, hipStream_t st) {
+                         double* result, hipStream_t st) {
   const int nt = tiles_of(g.n);
-  hipLaunchKernelGGL(k_dot_re, dim3(nt * batch), dim3(kBlock), 0, st, g, a, b, nt, part, counters, result);
+  hipLaunchKernelGGL(k_dot_re, dim3(nt * batch), dim3(kBlock), 0, st, g, a, b, nt, part);
+  hipLaunchKernelGGL(k_dot_finish, dim3(batch), dim3(kBlock), 0, st, part, nt, result);
   return hipGetLastError();
 }
 
@@ -718,6 +848,27 @@ hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, 
   return hipGetLastError();
 }
 
+hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
+                           hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(L.total_tiles), block(kBlock);
+  if (single) {
+    if (stage == 1)
+      hipExtLaunchKernelGGL((k_cg1<float, float>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R32, (int)S_P32,
+                            (int)S_U32);
+    else
+      hipExtLaunchKernelGGL((k_cg2<float, float>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R32, (int)S_P32,
+                            (int)S_U32);
+  } else {
+    if (stage == 1)
+      hipExtLaunchKernelGGL((k_cg1<double, double>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R, (int)S_P0,
+                            (int)S_U);
+    else
+      hipExtLaunchKernelGGL((k_cg2<double, double>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R, (int)S_P0,
+                            (int)S_U);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st) {
   const dim3 grid(L.total_tiles), block(kBlock);
   if (in_c64)
@@ -727,36 +878,65 @@ hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, b
   return hipGetLastError();
 }
 
+static hipError_t finish(const SysDesc* sys, const LaunchList& L, int nv, int red_off, RedMode mode,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(L.nsys), dim3(kBlock), 0, st, sys, L, nv, red_off, (int)mode);
+  return hipGetLastError();
+}
+
 hipError_t launch_normal2_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b, int s_out,
                                RedMode mode, int red_off, hipStream_t st) {
   const dim3 grid(L.total_tiles), block(kBlock);
   if (in_c64)
-    hipLaunchKernelGGL(k_normal2_slot<float2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode, red_off);
+    hipLaunchKernelGGL(k_normal2_slot<float2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
   else
-    hipLaunchKernelGGL(k_normal2_slot<double2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode, red_off);
-  return hipGetLastError();
+    hipLaunchKernelGGL(k_normal2_slot<double2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode == RED_NONE) return e;
+  return finish(sys, L, 1, red_off, mode, st);
 }
 
-hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, hipStream_t st) {
+hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, RedMode mode, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_init_zero, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(sys, L, 1, 0, mode, st);
 }
 
 hipError_t launch_multidot(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int red_off,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_multidot, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt, red_off);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_multidot, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(sys, L, 2 * cnt, red_off, RED_STORE, st);
 }
 
 hipError_t launch_cgs(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int h_off, int red_off,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_cgs, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt, h_off, red_off);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_cgs, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt, h_off);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return finish(sys, L, 1, red_off, RED_STORE, st);
 }
 
 hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src, int s_v, hipStream_t st) {
   hipLaunchKernelGGL(k_prep_inner, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_src, s_v);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // only systems that start a single-precision CG (pi > 0) are finalised
+  LaunchList F = L;
+  int m = 0;
+  for (int k = 0; k < L.nsys; ++k)
+    if (L.pi[k] > 0) {
+      F.sys[m] = L.sys[k];
+      F.pa[m] = 0.0;
+      F.pr[m] = L.pr[k];
+      F.pi[m] = L.pi[k];
+      ++m;
+    }
+  if (m == 0) return hipSuccess;
+  F.nsys = m;
+  return finish(sys, F, 1, 0, RED_CG_SETUP, st);
 }
 
 hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, int cnt, bool set, hipStream_t st) {

@@ -30,7 +30,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_submit", "hub_poll",
-              "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts"]:
+              "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts",
+              "hub_profile_enable", "hub_profile_read"]:
         assert f in names
 
 
@@ -53,6 +54,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(b.HubSolveInfo) == 24
     assert b.HubSolveInfo.true_rel_resid.offset == 16
     assert b.HubRequest.opts.offset == 80
+    assert ctypes.sizeof(b.HubKernelStat) == 40
 
 
 def test_default_options(lib):

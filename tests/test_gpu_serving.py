@@ -1,0 +1,124 @@
+"""Serving through hub_submit / hub_poll (continuous batching), on the GPU.
+
+* every request of a seeded mixed stream (lattice sizes, N_t, shifts) converges and
+  its solution meets the oracle's recomputed true residual;
+* each request's x, S and dS/dphi are bit-identical when it is served alone and when
+  it is served together with the rest of the stream (per-system reductions in a
+  fixed order, independent of the batch);
+* S and the force of a served request match the synchronous calls.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_07195_amd import binding as hb
+from tests.gpu_helpers import dev, host
+from workloads import draw_inputs, serving_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hub():
+    ctx = hb.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _requests(n, seed):
+    out = []
+    for r in serving_stream(n, seed=seed, Ls=(3, 6, 12, 24), Nts=(8, 16, 32)):
+        w = r["workload"]
+        phi, eta = draw_inputs(w)
+        hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+        ol = oracle.Lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+        chi = oracle.apply_Mdag(ol, phi, eta[0])
+        out.append((w, hl, ol, phi, chi))
+    return out
+
+
+def _wait(hub, pending, timeout=120.0):
+    t0 = time.time()
+    infos = {}
+    while len(infos) < len(pending):
+        for p in pending:
+            if p.ticket in infos:
+                continue
+            done, info = hb.hub_poll(hub, p)
+            if done:
+                infos[p.ticket] = info
+        assert time.time() - t0 < timeout, "serving did not finish"
+        time.sleep(0.001)
+    return [infos[p.ticket] for p in pending]
+
+
+def _submit(hub, reqs, opts):
+    pend = []
+    for (w, hl, ol, phi, chi) in reqs:
+        pend.append(hb.hub_submit(hub, hl, w.mu2[0], dev(phi), dev(chi[None]), opts=opts))
+    return pend
+
+
+@pytest.mark.parametrize("solver", ["fgmres", "cg"])
+def test_alone_vs_mix_bitwise(hub, solver):
+    reqs = _requests(16, seed=7)
+    opts = hb.default_opts(solver=solver, tol=1e-10)
+    alone = []
+    for r in reqs:
+        p = _submit(hub, [r], opts)
+        info = _wait(hub, p)[0]
+        alone.append((host(p[0].x).copy(), p[0].S, host(p[0].dS).copy(), info))
+    mix = _submit(hub, reqs, opts)
+    infos = _wait(hub, mix)
+    for k, (r, p, info) in enumerate(zip(reqs, mix, infos)):
+        w, hl, ol, phi, chi = r
+        xa, Sa, Fa, ia = alone[k]
+        assert info["converged"] == 1 and ia["converged"] == 1
+        x = host(p.x)
+        assert np.array_equal(x, xa), k
+        assert p.S == Sa, k
+        assert np.array_equal(host(p.dS), Fa), k
+        res = oracle.true_rel_residual(ol, phi, w.mu2[0], chi, x.reshape(chi.shape))
+        assert res <= 1e-10, (k, res)
+
+
+def test_served_outputs_match_synchronous_calls(hub):
+    reqs = _requests(6, seed=11)
+    opts = hb.default_opts(solver="fgmres")
+    pend = _submit(hub, reqs, opts)
+    _wait(hub, pend)
+    for r, p in zip(reqs, pend):
+        w, hl, ol, phi, chi = r
+        pd = dev(phi)
+        S = hb.hub_action(hub, hl, dev(chi[None]), p.x)[0]
+        assert S == p.S
+        F = hb.hub_force(hub, hl, pd, p.x)
+        assert torch.equal(F.reshape(p.dS.shape), p.dS)
+        Fo = oracle.force(ol, phi, host(p.x).reshape(chi.shape))
+        assert np.linalg.norm(host(p.dS) - Fo) <= 1e-8 * np.linalg.norm(Fo)
+
+
+def test_poll_unknown_ticket_and_release(hub):
+    with pytest.raises(hb.HubError):
+        hb.hub_poll(hub, 987654321)
+    reqs = _requests(1, seed=3)
+    p = _submit(hub, reqs, hb.default_opts())
+    _wait(hub, p)
+    # a ticket reported done is released
+    with pytest.raises(hb.HubError):
+        hb.hub_poll(hub, p[0])
+
+
+def test_request_over_budget_is_busy():
+    small = hb.Context(0, hbm_budget_bytes=1 << 20)
+    try:
+        w_phi = dev(np.zeros((64, 2, 48, 48)))
+        chi = dev(np.ones((1, 64, 2, 48, 48), complex))
+        with pytest.raises(hb.HubError) as e:
+            hb.hub_submit(small, hb.lattice(48, 48, 64, 0.2), 0.0, w_phi, chi, opts=hb.default_opts(solver="fgmres"))
+        assert e.value.status == hb.HUB_ERR_BUSY
+    finally:
+        small.close()
