@@ -71,6 +71,7 @@ struct System {
   int cycles = 0;
   int cg_total = 0;     // FP64 CG iterations over all restarts
   int enq = 0;          // CG iterations enqueued since the last CG setup
+  int gen = 0;          // number of CG setups so far (tags in-flight blocks)
   double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
   std::vector<std::complex<double>> H;  // (m+1) x m, column-major
   std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload
@@ -114,7 +115,20 @@ class Engine {
 
  private:
   hipError_t host_phase(System* s, bool& progressed);
-  hipError_t iterate(bool single);
+  // A block of CG iterations enqueued for the systems of one precision, whose
+  // convergence flags are read back asynchronously.
+  struct Block {
+    bool single = false;
+    int k = 0;
+    int buf = 0;
+    std::vector<System*> v;
+    std::vector<int> gen;               // System::gen of each system at enqueue
+    std::vector<std::vector<int>> its;  // iteration index per launch and system (profiling)
+    std::vector<hipEvent_t> kev;        // kernel start/stop events (profiling)
+    hipEvent_t done = nullptr;
+  };
+  hipError_t launch_block(bool single, bool& launched);
+  hipError_t finish_block(Block& b);
   hipError_t read_scal(const std::vector<System*>& v);
   hipError_t upload_desc(System* s);
   hipError_t upload_y(System* s, const std::vector<std::complex<double>>& y);
@@ -129,7 +143,10 @@ class Engine {
   Scal* h_scal_ = nullptr;      // pinned mirror
   std::vector<System*> slots_;
   bool profiling_ = false;
-  std::vector<hipEvent_t> events_;
+  std::vector<hipEvent_t> events_;      // pool for kernel timing
+  std::vector<Block> inflight_[2];      // per precision, oldest first
+  Scal* h_flags_ = nullptr;             // pinned, 4 buffers x kMaxSys
+  int next_buf_[2] = {0, 0};
 };
 
 std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& H, int ldh, int k,

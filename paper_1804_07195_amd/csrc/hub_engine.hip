@@ -194,6 +194,7 @@ Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSy
   hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys);
   hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys);
   hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault);
+  hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4, hipHostMallocDefault);
   hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_);
   std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
 }
@@ -212,6 +213,10 @@ Engine::~Engine() {
   hipFree(d_desc_);
   hipFree(d_scal_);
   hipHostFree(h_scal_);
+  hipHostFree(h_flags_);
+  for (auto& q : inflight_)
+    for (auto& b : q)
+      if (b.done) hipEventDestroy(b.done);
 }
 
 bool Engine::idle() const {
@@ -325,6 +330,15 @@ bool Engine::add(System* s) {
 }
 
 void Engine::remove(System* s) {
+  // drain blocks that still reference the system
+  for (auto& q : inflight_) {
+    bool refs = false;
+    for (auto& b : q)
+      for (System* x : b.v) refs = refs || x == s;
+    if (!refs) continue;
+    for (auto& b : q) finish_block(b);
+    q.clear();
+  }
   if (s->slot >= 0 && slots_[s->slot] == s) slots_[s->slot] = nullptr;
   for (void* p : s->owned) pool_->release(p, st_);
   s->owned.clear();
@@ -407,6 +421,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
           s->info.applies++;
         }
         s->enq = 0;
+        s->gen++;
         s->phase = PH_CG_ITER;
         return hipSuccess;
       }
@@ -448,6 +463,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       L.pj[0] = S_Z0;
       HUB_TRY(launch_prep_inner(d_desc_, L, S_R, -1, st_));
       s->enq = 0;
+      s->gen++;
       s->phase = PH_F_INNER;
       s->post = PH_F_POST_INIT;
       return hipSuccess;
@@ -471,6 +487,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       } else {
         s->info.outer_iters++;
         s->enq = 0;
+        s->gen++;
         s->phase = PH_CG_ITER;
       }
       return hipSuccess;
@@ -515,6 +532,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
         L.pi[0] = o.inner_max_iter;
         HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
         s->enq = 0;
+        s->gen++;
         s->phase = PH_F_INNER;
         s->post = PH_F_POST_ARNOLDI;
       } else {
@@ -582,8 +600,10 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
   }
 }
 
-// One block of CG iterations over every system that is iterating in the given precision.
-hipError_t Engine::iterate(bool single) {
+// Enqueue one block of CG iterations over every system that is iterating in the
+// given precision, followed by an asynchronous read-back of their flags.
+hipError_t Engine::launch_block(bool single, bool& launched) {
+  launched = false;
   std::vector<System*> v;
   int k = 1 << 30;
   for (System* s : slots_) {
@@ -594,15 +614,25 @@ hipError_t Engine::iterate(bool single) {
     }
   }
   if (v.empty()) return hipSuccess;
+  Block b;
+  b.single = single;
+  b.k = k;
+  b.v = v;
+  for (System* s : v) b.gen.push_back(s->gen);
+  b.buf = next_buf_[single ? 1 : 0];
+  next_buf_[single ? 1 : 0] ^= 1;
   LaunchList L = list(v);
-  for (size_t q = 0; q < v.size(); ++q) L.pi[q] = single ? S_Z0 + v[q]->j : S_X;
   // The solution slot of the initial single-precision solve is S_Z0 (j = 0 then).
-  std::vector<std::vector<int>> its;
+  for (size_t q = 0; q < v.size(); ++q) L.pi[q] = single ? S_Z0 + v[q]->j : S_X;
   if (profiling_) {
-    while ((int)events_.size() < 4 * k) {
-      hipEvent_t e;
-      HUB_TRY(hipEventCreate(&e));
-      events_.push_back(e);
+    for (int e = 0; e < 4 * k; ++e) {
+      if (events_.empty()) {
+        hipEvent_t ev;
+        HUB_TRY(hipEventCreate(&ev));
+        events_.push_back(ev);
+      }
+      b.kev.push_back(events_.back());
+      events_.pop_back();
     }
   }
   for (int it = 0; it < k; ++it) {
@@ -611,23 +641,44 @@ hipError_t Engine::iterate(bool single) {
       HUB_TRY(launch_cg_iter(d_desc_, L, single, st_));
       continue;
     }
-    its.emplace_back(L.it, L.it + v.size());
-    HUB_TRY(launch_cg_stage(d_desc_, L, single, 1, st_, events_[4 * it], events_[4 * it + 1]));
-    HUB_TRY(launch_cg_stage(d_desc_, L, single, 2, st_, events_[4 * it + 2], events_[4 * it + 3]));
+    b.its.emplace_back(L.it, L.it + v.size());
+    HUB_TRY(launch_cg_stage(d_desc_, L, single, 1, st_, b.kev[4 * it], b.kev[4 * it + 1]));
+    HUB_TRY(launch_cg_stage(d_desc_, L, single, 2, st_, b.kev[4 * it + 2], b.kev[4 * it + 3]));
   }
-  HUB_TRY(read_scal(v));
-  if (profiling_) {
+  int lo = kMaxSys, hi = -1;
+  for (System* s : v) {
+    lo = std::min(lo, s->slot);
+    hi = std::max(hi, s->slot);
+  }
+  Scal* dst = h_flags_ + (size_t)((single ? 2 : 0) + b.buf) * kMaxSys;
+  HUB_TRY(hipMemcpyAsync(dst + lo, d_scal_ + lo, sizeof(Scal) * (hi - lo + 1), hipMemcpyDeviceToHost, st_));
+  HUB_TRY(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+  HUB_TRY(hipEventRecord(b.done, st_));
+  inflight_[single ? 1 : 0].push_back(std::move(b));
+  launched = true;
+  return hipSuccess;
+}
+
+// Wait for a block's flags and move the systems that stopped iterating on.
+hipError_t Engine::finish_block(Block& b) {
+  const hipError_t w = hipEventSynchronize(b.done);
+  hipEventDestroy(b.done);
+  b.done = nullptr;
+  HUB_TRY(w);
+  const bool single = b.single;
+  const Scal* flags = h_flags_ + (size_t)((single ? 2 : 0) + b.buf) * kMaxSys;
+  if (profiling_ && !b.kev.empty()) {
     // A system did work in the launch of iteration `it` iff it < its final count
     // (or it is still iterating).
-    for (int it = 0; it < k; ++it) {
+    for (int it = 0; it < b.k; ++it) {
       double sites = 0.0;
-      for (size_t q = 0; q < v.size(); ++q) {
-        const Scal& sc = h_scal_[v[q]->slot];
-        if (sc.active || its[it][q] < sc.iters) sites += (double)v[q]->g.n;
+      for (size_t q = 0; q < b.v.size(); ++q) {
+        const Scal& sc = flags[b.v[q]->slot];
+        if (sc.active || b.its[it][q] < sc.iters) sites += (double)b.v[q]->g.n;
       }
       for (int stage = 0; stage < 2; ++stage) {
         float ms = 0.0f;
-        HUB_TRY(hipEventElapsedTime(&ms, events_[4 * it + 2 * stage], events_[4 * it + 2 * stage + 1]));
+        HUB_TRY(hipEventElapsedTime(&ms, b.kev[4 * it + 2 * stage], b.kev[4 * it + 2 * stage + 1]));
         KernelStat& ks = stat[single ? 1 : 0][stage];
         ks.launches++;
         ks.ms += ms;
@@ -635,8 +686,15 @@ hipError_t Engine::iterate(bool single) {
       }
     }
   }
-  for (System* s : v) {
-    const Scal& sc = h_scal_[s->slot];
+  for (hipEvent_t e : b.kev) events_.push_back(e);
+  b.kev.clear();
+  for (size_t q = 0; q < b.v.size(); ++q) {
+    System* s = b.v[q];
+    const bool want = single ? (s->phase == PH_F_INNER) : (s->phase == PH_CG_ITER);
+    // skip a system that an earlier block already moved on (its flags here
+    // belong to a finished CG run)
+    if (s->done || !want || s->gen != b.gen[q]) continue;
+    const Scal& sc = flags[s->slot];
     if (sc.active) continue;
     if (single) {
       s->info.inner_iters += sc.iters;
@@ -652,6 +710,22 @@ hipError_t Engine::iterate(bool single) {
 }
 
 hipError_t Engine::step() {
+  // 1. keep the GPU busy: enqueue the next block for every system still iterating
+  //    (speculatively: a system that converged in the block still in flight runs
+  //    empty launches, which return at once)
+  bool launched[2] = {false, false};
+  HUB_TRY(launch_block(false, launched[0]));
+  HUB_TRY(launch_block(true, launched[1]));
+  // 2. read back older blocks: keep one in flight while that precision iterates
+  for (int k = 0; k < 2; ++k) {
+    auto& q = inflight_[k];
+    const size_t keep = launched[k] ? 1 : 0;
+    while (q.size() > keep) {
+      HUB_TRY(finish_block(q.front()));
+      q.erase(q.begin());
+    }
+  }
+  // 3. host-side phases of the systems that are not iterating
   bool progressed = true;
   while (progressed) {
     progressed = false;
@@ -662,14 +736,11 @@ hipError_t Engine::step() {
       progressed = progressed || p;
       if (s->done && s->on_done) s->on_done(s);
     }
-    // stop once every live system is iterating or done
     bool all_wait = true;
     for (System* s : slots_)
       if (s && !s->done && s->phase != PH_F_INNER && s->phase != PH_CG_ITER) all_wait = false;
     if (all_wait) break;
   }
-  HUB_TRY(iterate(false));
-  HUB_TRY(iterate(true));
   return hipSuccess;
 }
 

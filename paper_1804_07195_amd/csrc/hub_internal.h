@@ -10,7 +10,10 @@
 namespace hub {
 
 constexpr int kBlock = 256;                   // threads per workgroup (4 wave64)
-constexpr int kSitesPerThread = 4;            // sites handled by each thread
+#ifndef HUB_SITES_PER_THREAD
+#define HUB_SITES_PER_THREAD 4
+#endif
+constexpr int kSitesPerThread = HUB_SITES_PER_THREAD;  // sites handled by each thread
 constexpr int kTile = kBlock * kSitesPerThread;  // sites per workgroup tile
 constexpr int kMaxSys = 64;                   // systems per batched launch
 constexpr int kMaxRestart = 20;               // largest FGMRES restart length

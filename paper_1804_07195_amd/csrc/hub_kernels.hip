@@ -26,10 +26,10 @@ namespace {
 
 // Sites whose loads are issued together (per thread) in the stencil kernels.
 #ifndef HUB_SPT64
-#define HUB_SPT64 2
+#define HUB_SPT64 (HUB_SITES_PER_THREAD < 2 ? HUB_SITES_PER_THREAD : 2)
 #endif
 #ifndef HUB_SPT32
-#define HUB_SPT32 4
+#define HUB_SPT32 (HUB_SITES_PER_THREAD < 4 ? HUB_SITES_PER_THREAD : 4)
 #endif
 template <typename R> struct Spt;
 template <> struct Spt<double> { static constexpr int v = HUB_SPT64; };
@@ -79,9 +79,31 @@ template <> struct Vec<double2> {
     p[k] = v;
   }
 };
+typedef float hub_f4v __attribute__((ext_vector_type(4)));
+// Two consecutive complex64 values (sites k, k+1 with k even: one 16-byte access).
+struct C64x2 {
+  float2 a, b;
+};
 template <> struct Vec<float2> {
   HUB_GAS hub_f2v* p;
   __device__ __forceinline__ explicit Vec(const void* q) : p((HUB_GAS hub_f2v*)q) {}
+  __device__ __forceinline__ C64x2 pair(int k) const {
+    const hub_f4v v = ((HUB_GAS hub_f4v*)p)[k >> 1];
+    C64x2 r;
+    r.a.x = v.x;
+    r.a.y = v.y;
+    r.b.x = v.z;
+    r.b.y = v.w;
+    return r;
+  }
+  __device__ __forceinline__ void set_pair(int k, C64x2 a) const {
+    hub_f4v v;
+    v.x = a.a.x;
+    v.y = a.a.y;
+    v.z = a.b.x;
+    v.w = a.b.y;
+    ((HUB_GAS hub_f4v*)p)[k >> 1] = v;
+  }
   __device__ __forceinline__ float2 operator[](int k) const {
     const hub_f2v v = p[k];
     float2 r;
@@ -101,70 +123,19 @@ template <typename T> struct Real {
   __device__ __forceinline__ explicit Real(const void* q) : p((HUB_GAS T*)q) {}
   __device__ __forceinline__ T operator[](int k) const { return p[k]; }
   __device__ __forceinline__ void set(int k, T v) const { p[k] = v; }
+  // values at k, k+1 (k even): one 8-byte access for float
+  __device__ __forceinline__ hub_f2v pair(int k) const { return ((HUB_GAS hub_f2v*)p)[k >> 1]; }
 };
 
-// The stencil of M (DAG = false) or M^dagger (DAG = true) at site n.
+// The stencil of M (DAG = false) or M^dagger (DAG = true) at site n (eq. (ferm_op) and its
+// conjugate transpose):
 //   M,  A row: -x(n) + s (e^{ i phi(n)}  - m) x(t-1) - kappa sum_bonds x_B
 //   M,  B row: +x(n) - s (e^{-i phi(n)}  - m) x(t+1) - kappa sum_bonds x_A
 //   M+, A row: -x(n) + s (e^{-i phi(tn)} - m) x(t+1) - kappa sum_bonds x_B
 //   M+, B row: +x(n) - s (e^{ i phi(tn)} - m) x(t-1) - kappa sum_bonds x_A
-// with s = -1 on a hop across the antiperiodic temporal boundary.  `ld(k)` returns
-// the input vector at site k; the own-site value is returned in `self`.
-template <typename R, bool DAG, typename Phi, typename Load>
-__device__ __forceinline__ typename V2<R>::T stencil(const Geom& g, const Phi& phi, int n, Load ld,
-                                                     typename V2<R>::T& self) {
-  using C = typename V2<R>::T;
-  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
-  const int j = n - (int)q1 * g.L2;
-  const uint32_t q2 = fdiv(q1, g.dL1);
-  const int i = (int)q1 - (int)q2 * g.L1;
-  const bool isA = (q2 & 1u) == 0;
-  const int t = (int)(q2 >> 1);
-  const int P2 = 2 * g.P;
-  const bool fwd = (isA == DAG);
-  int tn;
-  R sgn;
-  if (fwd) {
-    const bool wrap = t == g.Nt - 1;
-    tn = wrap ? n - (g.Nt - 1) * P2 : n + P2;
-    sgn = wrap ? R(-1) : R(1);
-  } else {
-    const bool wrap = t == 0;
-    tn = wrap ? n + (g.Nt - 1) * P2 : n - P2;
-    sgn = wrap ? R(-1) : R(1);
-  }
-  int h0, h1, h2;
-  if (isA) {
-    const int b = n + g.P;
-    h0 = b;
-    h1 = (i > 0) ? b - g.L2 : b + (g.L1 - 1) * g.L2;
-    h2 = (j > 0) ? b - 1 : b + g.L2 - 1;
-  } else {
-    const int a = n - g.P;
-    h0 = a;
-    h1 = (i < g.L1 - 1) ? a + g.L2 : a - (g.L1 - 1) * g.L2;
-    h2 = (j < g.L2 - 1) ? a + 1 : a - (g.L2 - 1);
-  }
-  const C xs = ld(n);
-  const C xt = ld(tn);
-  const C x0 = ld(h0);
-  const C x1 = ld(h1);
-  const C x2 = ld(h2);
-  R c, s;
-  phase_cs((R)phi[DAG ? tn : n], c, s);
-  const R es = (isA != DAG) ? s : -s;          // e^{+i phi} iff A row of M or B row of M^dagger
-  const R cr = sgn * (c - (R)g.ms), ci = sgn * es;
-  const R tr = cr * xt.x - ci * xt.y, ti = cr * xt.y + ci * xt.x;
-  const R sig = isA ? R(-1) : R(1);
-  const R kap = (R)g.kappa;
-  C y;
-  y.x = sig * (xs.x - tr) - kap * (x0.x + x1.x + x2.x);
-  y.y = sig * (xs.y - ti) - kap * (x0.y + x1.y + x2.y);
-  self = xs;
-  return y;
-}
-
-// Index part of the stencil at site n (see `stencil`): own site, temporal
+// with s = -1 on a hop across the antiperiodic temporal boundary.
+//
+// Index part of the stencil at site n: own site, temporal
 // neighbour, three bonds, the phi index and the row's signs.
 struct SiteIdx {
   int n, tn, h0, h1, h2, pn;
@@ -224,18 +195,23 @@ __device__ __forceinline__ C stencil_combine(const Geom& g, const SiteIdx& st, R
 
 // Apply the stencil to the kSitesPerThread sites of this thread in a tile, SPT
 // sites at a time: all index arithmetic first, then every load of the SPT sites
-// (stencil inputs, phi and the epilogue's own operands from `pre`), then the
-// arithmetic and `post(n, y, self, pre_value)`.  Issuing the loads of several sites
-// before the first wait keeps enough bytes in flight to cover HBM latency.  Lanes
+// (raw stencil inputs `ld`, phi and the epilogue's own operands `pre`), then, in
+// the first round only, `mid()` (which may compute scalars from partial sums and
+// returns false to skip the rest), then `cook(raw)` turns raw loads into stencil
+// inputs, the arithmetic, and `post(n, y, self, pre_value)`.  Issuing the loads
+// of several sites before the first wait keeps enough bytes in flight to cover
+// HBM latency, and the partial-sum prologue of `mid` overlaps those loads.  Lanes
 // past the end of the vector load a valid site and skip `post`.
-template <typename R, bool DAG, int SPT, typename Phi, typename Load, typename Pre, typename Post>
-__device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int base, Load ld, Pre pre,
-                                              Post post) {
+template <typename R, bool DAG, int SPT, int TOTAL = kSitesPerThread, typename Phi, typename Load, typename Cook,
+          typename Pre, typename Mid, typename Post>
+__device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int base, Load ld, Cook cook, Pre pre,
+                                              Mid mid, Post post) {
   using C = typename V2<R>::T;
+  using RW = decltype(ld(0));
   using PV = decltype(pre(0));
-  static_assert(kSitesPerThread % SPT == 0, "SPT must divide kSitesPerThread");
+  static_assert(TOTAL % SPT == 0, "SPT must divide TOTAL");
 #pragma unroll
-  for (int r0 = 0; r0 < kSitesPerThread; r0 += SPT) {
+  for (int r0 = 0; r0 < TOTAL; r0 += SPT) {
     SiteIdx st[SPT];
     bool ok[SPT];
 #pragma unroll
@@ -245,7 +221,7 @@ __device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int
       n = ok[m] ? n : g.n - 1;
       st[m] = site_index<DAG>(g, n);
     }
-    C xs[SPT], xt[SPT], x0[SPT], x1[SPT], x2[SPT];
+    RW xs[SPT], xt[SPT], x0[SPT], x1[SPT], x2[SPT];
     R ph[SPT];
     PV pv[SPT];
 #pragma unroll
@@ -258,17 +234,155 @@ __device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int
       ph[m] = (R)phi[st[m].pn];
       pv[m] = pre(st[m].n);
     }
+    if (r0 == 0 && !mid()) return;
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
-      const C y = stencil_combine<R, DAG>(g, st[m], ph[m], xs[m], xt[m], x0[m], x1[m], x2[m]);
-      if (ok[m]) post(st[m].n, y, xs[m], pv[m]);
+      const C s0 = cook(xs[m]);
+      const C y = stencil_combine<R, DAG>(g, st[m], ph[m], s0, cook(xt[m]), cook(x0[m]), cook(x1[m]),
+                                          cook(x2[m]));
+      if (ok[m]) post(st[m].n, y, s0, pv[m]);
     }
   }
 }
 
+struct NoMid {
+  __device__ __forceinline__ bool operator()() const { return true; }
+};
+struct Same {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T v) const {
+    return v;
+  }
+};
+
 struct NoPre {
   int dummy;
 };
+
+// ---------------------------------------------------------------------------
+// Complex64 stencil on site pairs (j, j+1), j even, for lattices with even L2.
+// A pair never straddles a row, so the own values, the temporal neighbours, the
+// sublattice partners and the i-neighbour row are 16-byte loads of two sites; of
+// the j-bonds one is the partner load's other half and one is an extra 8-byte
+// load.  This halves the memory instructions per site of the complex64 kernels.
+// ---------------------------------------------------------------------------
+struct PairIdx {
+  int n, tn, h0, h1, hx;
+  bool isA, wrap;
+};
+
+template <bool DAG>
+__device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
+  PairIdx s;
+  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
+  const int j = n - (int)q1 * g.L2;
+  const uint32_t q2 = fdiv(q1, g.dL1);
+  const int i = (int)q1 - (int)q2 * g.L1;
+  s.isA = (q2 & 1u) == 0;
+  const int t = (int)(q2 >> 1);
+  const int P2 = 2 * g.P;
+  if (s.isA == DAG) {
+    s.wrap = t == g.Nt - 1;
+    s.tn = s.wrap ? n - (g.Nt - 1) * P2 : n + P2;
+  } else {
+    s.wrap = t == 0;
+    s.tn = s.wrap ? n + (g.Nt - 1) * P2 : n - P2;
+  }
+  if (s.isA) {
+    const int b = n + g.P;
+    s.h0 = b;
+    s.h1 = (i > 0) ? b - g.L2 : b + (g.L1 - 1) * g.L2;
+    s.hx = (j > 0) ? b - 1 : b + g.L2 - 1;  // B(i, j-1)
+  } else {
+    const int a = n - g.P;
+    s.h0 = a;
+    s.h1 = (i < g.L1 - 1) ? a + g.L2 : a - (g.L1 - 1) * g.L2;
+    s.hx = (j + 2 < g.L2) ? a + 2 : a + 2 - g.L2;  // A(i, j+2)
+  }
+  s.n = n;
+  return s;
+}
+
+// Apply M (DAG = false) or M^dagger to the kSitesPerThread/2 site pairs of this
+// thread in a tile: pairs base_pair + threadIdx.x + m*kBlock.  ld2(k) loads the raw
+// input at k, k+1 and ld1(k) at k; after `mid()` (see stencil_sites), cook2 / cook1
+// turn them into C64x2 / float2 inputs; post(n, y, self, pre) per pair.
+template <bool DAG, typename Phi, typename Ld2, typename Ld1, typename Cook2, typename Cook1, typename Pre,
+          typename Mid, typename Post>
+__device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int tile, Ld2 ld2, Ld1 ld1,
+                                              Cook2 cook2, Cook1 cook1, Pre pre, Mid mid, Post post) {
+  using PV = decltype(pre(0));
+  using R2 = decltype(ld2(0));
+  using R1 = decltype(ld1(0));
+  constexpr int NP = kSitesPerThread / 2;
+  PairIdx st[NP];
+  bool ok[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    int n = tile * kTile + 2 * (threadIdx.x + m * kBlock);
+    ok[m] = n < g.n;
+    n = ok[m] ? n : g.n - 2;
+    st[m] = pair_index<DAG>(g, n);
+  }
+  R2 rs[NP], rt[NP], r0[NP], r1[NP];
+  R1 re[NP];
+  hub_f2v ph[NP];
+  PV pv[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    rs[m] = ld2(st[m].n);
+    rt[m] = ld2(st[m].tn);
+    r0[m] = ld2(st[m].h0);
+    r1[m] = ld2(st[m].h1);
+    re[m] = ld1(st[m].hx);
+    ph[m] = phi.pair(DAG ? st[m].tn : st[m].n);
+    pv[m] = pre(st[m].n);
+  }
+  if (!mid()) return;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const PairIdx& sm = st[m];
+    const C64x2 xs = cook2(rs[m]), xt = cook2(rt[m]), x0 = cook2(r0[m]), x1 = cook2(r1[m]);
+    const float2 xe = cook1(re[m]);
+    // bond sums of the two sites
+    float2 b0, b1;
+    if (sm.isA) {
+      b0.x = x0.a.x + x1.a.x + xe.x;
+      b0.y = x0.a.y + x1.a.y + xe.y;
+      b1.x = x0.b.x + x1.b.x + x0.a.x;
+      b1.y = x0.b.y + x1.b.y + x0.a.y;
+    } else {
+      b0.x = x0.a.x + x1.a.x + x0.b.x;
+      b0.y = x0.a.y + x1.a.y + x0.b.y;
+      b1.x = x0.b.x + x1.b.x + xe.x;
+      b1.y = x0.b.y + x1.b.y + xe.y;
+    }
+    const float sgn = sm.wrap ? -1.0f : 1.0f;
+    const float sig = sm.isA ? -1.0f : 1.0f;
+    const float kap = (float)g.kappa, mst = (float)g.ms;
+    const bool plus = (sm.isA != DAG);
+    C64x2 y;
+    {
+      float c, s;
+      phase_cs(ph[m].x, c, s);
+      const float es = plus ? s : -s;
+      const float cr = sgn * (c - mst), ci = sgn * es;
+      const float tr = cr * xt.a.x - ci * xt.a.y, ti = cr * xt.a.y + ci * xt.a.x;
+      y.a.x = sig * (xs.a.x - tr) - kap * b0.x;
+      y.a.y = sig * (xs.a.y - ti) - kap * b0.y;
+    }
+    {
+      float c, s;
+      phase_cs(ph[m].y, c, s);
+      const float es = plus ? s : -s;
+      const float cr = sgn * (c - mst), ci = sgn * es;
+      const float tr = cr * xt.b.x - ci * xt.b.y, ti = cr * xt.b.y + ci * xt.b.x;
+      y.b.x = sig * (xs.b.x - tr) - kap * b1.x;
+      y.b.y = sig * (xs.b.y - ti) - kap * b1.y;
+    }
+    if (ok[m]) post(sm.n, y, xs, pv[m]);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -317,8 +431,12 @@ __device__ __forceinline__ void store_active(Scal* sc, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Public operator kernels (shared phi, batch of vectors, no descriptors).
+// Public operator kernels (shared phi, batch of vectors, no descriptors).  They
+// have no reduction partials, so they use smaller tiles (two sites per thread,
+// both loaded together): more waves in flight than the CG kernels' tiles.
 // ---------------------------------------------------------------------------
+constexpr int kPubSites = 2;
+constexpr int kPubTile = kBlock * kPubSites;
 template <bool DAG>
 __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restrict__ phi,
                                                   const double2* __restrict__ x, double2* __restrict__ y,
@@ -327,11 +445,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   const int b = l / ntiles, tile = l - b * ntiles;
   const double2* __restrict__ xb = x + (size_t)b * g.n;
   double2* __restrict__ yb = y + (size_t)b * g.n;
-  const int base = tile * kTile + threadIdx.x;
+  const int base = tile * kPubTile + threadIdx.x;
   auto ld = [=](int k) { return xb[k]; };
   auto pre = [](int) { return NoPre{}; };
   auto post = [=](int n, double2 v, double2, NoPre) { yb[n] = v; };
-  stencil_sites<double, DAG, Spt<double>::v>(g, phi, base, ld, pre, post);
+  stencil_sites<double, DAG, kPubSites, kPubSites>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
 }
 
 struct Mu2Arr { double v[kMaxSys]; };
@@ -344,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
   const int b = l / ntiles, tile = l - b * ntiles;
   const size_t off = (size_t)b * g.n;
   const double m2 = mu2.v[b];
-  const int base = tile * kTile + threadIdx.x;
+  const int base = tile * kPubTile + threadIdx.x;
   auto ld = [=](int k) { return u[off + k]; };
   auto pre = [=](int n) { return x[off + n]; };
   auto post = [=](int n, double2 q, double2, double2 xv) {
@@ -352,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
     q.y += m2 * xv.y;
     y[off + n] = q;
   };
-  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, pre, post);
+  stencil_sites<double, false, kPubSites, kPubSites>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
 }
 
 // dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} xi(t-1)],
@@ -447,6 +565,12 @@ __global__ __launch_bounds__(kBlock) void k_phi_to_f32(const double* __restrict_
 //   |r_it|^2 from the stage-2 partials of iteration it-1 (it > 0) and the stopping
 //   test; p_new = r + beta p_old with beta = |r_it|^2 / |r_{it-1}|^2 (p_new = r at
 //   it = 0), u = M^dagger p_new, partial of |u|^2 + mu^2 |p_new|^2 = <p, A p>.
+// The loads of r and p_old are issued before the partial sums are read.
+template <typename C>
+struct RP {
+  C r, p;
+};
+
 template <typename R, typename PhiT>
 __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
                                                 int sU) {
@@ -454,8 +578,14 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
   HUB_PROLOGUE
   if (!load_active(sc)) return;
   const int it = L.it[kk];
+  const R mu2 = (R)d->mu2;
+  const Vec<C> r(d->vec[sR]), po(d->vec[sP + (it & 1)]), pn(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]);
+  const Real<PhiT> phi = phi_of<PhiT>(d);
   R beta = 0;
-  if (it > 0) {
+  bool stopped = false;  // same value in every thread of every workgroup of the system
+  // |r_it|^2, the stopping test and beta, once the stencil loads are in flight
+  auto mid = [&]() -> bool {
+    if (it == 0) return true;
     const double rr = sum_partials(d->part2, d->ntiles, 1);
     const double rr_prev = sc->rrv[(it - 1) & 1];
     const bool first = (tile == 0 && threadIdx.x == 0);
@@ -465,41 +595,79 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
         sc->iters = it;
         store_active(sc, 0);
       }
-      return;
+      stopped = true;
+      return false;
     }
     if (first) sc->rrv[it & 1] = rr;
     beta = (R)(rr / rr_prev);
-  }
-  const R mu2 = (R)d->mu2;
-  const Vec<C> r(d->vec[sR]), po(d->vec[sP + (it & 1)]), pn(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]);
-  const Real<PhiT> phi = phi_of<PhiT>(d);
-  R acc = 0;
-  auto pre = [](int) { return NoPre{}; };
-  auto post = [&](int n, C uu, C p, NoPre) {
-    pn.set(n, p);
-    u.set(n, uu);
-    acc += norm2<R>(uu) + mu2 * norm2<R>(p);
+    return true;
   };
-  if (it == 0) {
-    auto ld = [=](int k) { return r[k]; };
-    stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, pre, post);
-  } else {
-    auto ld = [=](int k) {
-      const C a = r[k], b = po[k];
-      C o;
-      o.x = a.x + beta * b.x;
-      o.y = a.y + beta * b.y;
-      return o;
-    };
-    stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, pre, post);
+  R acc = 0;
+  bool done = false;
+  if constexpr (sizeof(R) == 4) {
+    if ((g.L2 & 1) == 0) {
+      auto pre2 = [](int) { return NoPre{}; };
+      auto post2 = [&](int n, C64x2 uu, C64x2 p, NoPre) {
+        pn.set_pair(n, p);
+        u.set_pair(n, uu);
+        acc += norm2<R>(uu.a) + norm2<R>(uu.b) + mu2 * (norm2<R>(p.a) + norm2<R>(p.b));
+      };
+      if (it == 0) {
+        auto ld2 = [=](int k) { return r.pair(k); };
+        auto ld1 = [=](int k) { return r[k]; };
+        stencil_pairs<true>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, NoMid{}, post2);
+      } else {
+        auto ld2 = [=](int k) { return RP<C64x2>{r.pair(k), po.pair(k)}; };
+        auto ld1 = [=](int k) { return RP<C>{r[k], po[k]}; };
+        auto cook2 = [&](RP<C64x2> v) {
+          C64x2 o;
+          o.a.x = v.r.a.x + beta * v.p.a.x;
+          o.a.y = v.r.a.y + beta * v.p.a.y;
+          o.b.x = v.r.b.x + beta * v.p.b.x;
+          o.b.y = v.r.b.y + beta * v.p.b.y;
+          return o;
+        };
+        auto cook1 = [&](RP<C> v) {
+          C o;
+          o.x = v.r.x + beta * v.p.x;
+          o.y = v.r.y + beta * v.p.y;
+          return o;
+        };
+        stencil_pairs<true>(g, phi, tile, ld2, ld1, cook2, cook1, pre2, mid, post2);
+      }
+      done = true;
+    }
   }
+  if (!done) {
+    auto pre = [](int) { return NoPre{}; };
+    auto post = [&](int n, C uu, C p, NoPre) {
+      pn.set(n, p);
+      u.set(n, uu);
+      acc += norm2<R>(uu) + mu2 * norm2<R>(p);
+    };
+    if (it == 0) {
+      auto ld = [=](int k) { return r[k]; };
+      stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+    } else {
+      auto ld = [=](int k) { return RP<C>{r[k], po[k]}; };
+      auto cook = [&](RP<C> v) {
+        C o;
+        o.x = v.r.x + beta * v.p.x;
+        o.y = v.r.y + beta * v.p.y;
+        return o;
+      };
+      stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, cook, pre, mid, post);
+    }
+  }
+  // a system that met its stopping test in `mid` writes no partial (none is read)
+  if (stopped) return;
   const double tot = (double)block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part1).set(tile, tot);
 }
 
 // CG stage 2 of iteration it: alpha = |r_it|^2 / <p, A p> (stage-1 partials),
 // q = M u + mu^2 p, x += alpha p, r -= alpha q, partial of |r_{it+1}|^2.
-// The solution slot of system k is L.pi[k].
+// The solution slot of system k is L.pi[k].  Loads are issued before alpha is read.
 template <typename R, typename PhiT>
 __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
                                                 int sU) {
@@ -507,30 +675,68 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
   HUB_PROLOGUE
   if (!load_active(sc)) return;
   const int it = L.it[kk];
-  const double pq = sum_partials(d->part1, d->ntiles, 1);
-  const R alpha = (R)(sc->rrv[it & 1] / pq);
+  R alpha = 0;
+  auto mid = [&]() -> bool {
+    const double pq = sum_partials(d->part1, d->ntiles, 1);
+    alpha = (R)(sc->rrv[it & 1] / pq);
+    return true;
+  };
   const R mu2 = (R)d->mu2;
   const Vec<C> p(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]), x(d->vec[L.pi[kk]]), r(d->vec[sR]);
   const Real<PhiT> phi = phi_of<PhiT>(d);
-  auto ld = [=](int k) { return u[k]; };
   struct Own {
     C p, x, r;
   };
-  auto pre = [=](int n) { return Own{p[n], x[n], r[n]}; };
   R acc = 0;
-  auto post = [&](int n, C q, C, Own o) {
-    q.x += mu2 * o.p.x;
-    q.y += mu2 * o.p.y;
-    C xv = o.x, rv = o.r;
-    xv.x += alpha * o.p.x;
-    xv.y += alpha * o.p.y;
-    rv.x -= alpha * q.x;
-    rv.y -= alpha * q.y;
-    x.set(n, xv);
-    r.set(n, rv);
-    acc += norm2<R>(rv);
-  };
-  stencil_sites<R, false, Spt<R>::v>(g, phi, base, ld, pre, post);
+  bool done = false;
+  if constexpr (sizeof(R) == 4) {
+    if ((g.L2 & 1) == 0) {
+      struct Own2 {
+        C64x2 p, x, r;
+      };
+      auto ld2 = [=](int k) { return u.pair(k); };
+      auto ld1 = [=](int k) { return u[k]; };
+      auto pre2 = [=](int n) { return Own2{p.pair(n), x.pair(n), r.pair(n)}; };
+      auto post2 = [&](int n, C64x2 q, C64x2, Own2 o) {
+        C64x2 xv, rv;
+        C qa = q.a, qb = q.b;
+        qa.x += mu2 * o.p.a.x;
+        qa.y += mu2 * o.p.a.y;
+        qb.x += mu2 * o.p.b.x;
+        qb.y += mu2 * o.p.b.y;
+        xv.a.x = o.x.a.x + alpha * o.p.a.x;
+        xv.a.y = o.x.a.y + alpha * o.p.a.y;
+        xv.b.x = o.x.b.x + alpha * o.p.b.x;
+        xv.b.y = o.x.b.y + alpha * o.p.b.y;
+        rv.a.x = o.r.a.x - alpha * qa.x;
+        rv.a.y = o.r.a.y - alpha * qa.y;
+        rv.b.x = o.r.b.x - alpha * qb.x;
+        rv.b.y = o.r.b.y - alpha * qb.y;
+        x.set_pair(n, xv);
+        r.set_pair(n, rv);
+        acc += norm2<R>(rv.a) + norm2<R>(rv.b);
+      };
+      stencil_pairs<false>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
+      done = true;
+    }
+  }
+  if (!done) {
+    auto ld = [=](int k) { return u[k]; };
+    auto pre = [=](int n) { return Own{p[n], x[n], r[n]}; };
+    auto post = [&](int n, C q, C, Own o) {
+      q.x += mu2 * o.p.x;
+      q.y += mu2 * o.p.y;
+      C xv = o.x, rv = o.r;
+      xv.x += alpha * o.p.x;
+      xv.y += alpha * o.p.y;
+      rv.x -= alpha * q.x;
+      rv.y -= alpha * q.y;
+      x.set(n, xv);
+      r.set(n, rv);
+      acc += norm2<R>(rv);
+    };
+    stencil_sites<R, false, Spt<R>::v>(g, phi, base, ld, Same{}, pre, mid, post);
+  }
   const double tot = (double)block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }
@@ -555,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_mdag_slot(const SysDesc* __restrict_
   auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
   auto pre = [](int) { return NoPre{}; };
   auto post = [=](int n, double2 v, double2, NoPre) { u.set(n, v); };
-  stencil_sites<double, true, Spt<double>::v>(g, phi, base, ld, pre, post);
+  stencil_sites<double, true, Spt<double>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
 }
 
 __device__ __forceinline__ void store_partials(const SysDesc* d, int tile, const double* vals, int nv) {
@@ -592,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_normal2_slot(const SysDesc* __restri
     out.set(n, q);
     acc += norm2<double>(q);
   };
-  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, pre, post);
+  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
   if (mode == RED_NONE) return;
   const double tot = block_sum(acc);
   store_partials(d, tile, &tot, 1);
@@ -798,7 +1004,7 @@ static inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }
 
 hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
                         hipStream_t st) {
-  const int nt = tiles_of(g.n);
+  const int nt = (g.n + kPubTile - 1) / kPubTile;
   const dim3 grid(nt * batch), block(kBlock);
   if (dag)
     hipLaunchKernelGGL(k_apply<true>, grid, block, 0, st, g, phi, x, y, nt);
@@ -809,7 +1015,7 @@ hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, doub
 
 hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
                           const double2* x, double2* y, int batch, hipStream_t st) {
-  const int nt = tiles_of(g.n);
+  const int nt = (g.n + kPubTile - 1) / kPubTile;
   Mu2Arr m;
   for (int b = 0; b < kMaxSys; ++b) m.v[b] = b < batch ? mu2_host[b] : 0.0;
   hipLaunchKernelGGL(k_normal2_pub, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, m, u, x, y, nt);
