@@ -18,17 +18,22 @@ complex128 / float64 with NumPy and SciPy sparse matrices:
                 (Algorithm A.1) as a method oracle for iteration counts;
 * `force`     - the pseudofermion action S = chi^dagger (M M^dagger)^{-1} chi of
                 eq. (hamiltonian) and its derivative dS/dphi from eqs. (p_dot),
-                (eta_xi), contracting the explicit derivative of M.
+                (eta_xi), contracting the explicit derivative of M;
+* `hasenbusch` - the staggered-mass Hasenbusch split of Sec. 5.1: heat-bath of the
+                n+1 pseudofermions, the per-term actions and the ratio forces of
+                eq. (f_chi_i).
 
-Every function is pinned by a test in `tests/test_oracle_pins.py` against a
+Every function is pinned by a test in `tests/test_oracle_pins.py` or
+`tests/test_oracle_hasenbusch.py` against a
 closed form, an invariance or brute force that does not reuse its code.
 """
 from .operator import Lattice, build_M, build_M_dense_loops, apply_M, apply_Mdag, normal_apply, site_index
 from .solve import solve, solve_dense, cg, true_rel_residual, fgmres_alg_a1
 from .force import action, force, xi_from_eta
+from . import hasenbusch
 
 __all__ = [
     "Lattice", "build_M", "build_M_dense_loops", "apply_M", "apply_Mdag", "normal_apply", "site_index",
     "solve", "solve_dense", "cg", "true_rel_residual", "fgmres_alg_a1",
-    "action", "force", "xi_from_eta",
+    "action", "force", "xi_from_eta", "hasenbusch",
 ]

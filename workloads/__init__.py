@@ -21,7 +21,8 @@ import math
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "draw_phi", "draw_gaussian_c128", "draw_inputs"]
+__all__ = ["Workload", "WORKLOADS", "HasenbuschWorkload", "HASENBUSCH", "draw_phi", "draw_gaussian_c128",
+           "draw_inputs", "draw_hasenbusch"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -93,6 +94,32 @@ WORKLOADS = {
 }
 
 
+@dataclasses.dataclass(frozen=True)
+class HasenbuschWorkload:
+    """A lattice with n staggered Hasenbusch masses mu_0 < ... < mu_{n-1} (units of kappa)."""
+
+    base: Workload
+    masses: tuple
+
+    @property
+    def mts(self) -> list:
+        """m~_i = delta * mu_i, the parameter of M(m_s = mu_i)."""
+        return [self.base.delta * m for m in self.masses]
+
+    @property
+    def nterms(self) -> int:
+        return len(self.masses) + 1
+
+
+# The masses of the paper's auto-tuned two-mass runs (Table tab_nmds): at 12x12 and
+# 102x102 with N_t = 64; the small case uses the 12x12 pair on the 12x12, N_t = 32 lattice.
+HASENBUSCH = {
+    "hb_tiny": HasenbuschWorkload(Workload("hb_tiny", 3, 3, 8, 1.0, 2.0, 4.0, seed=20), (0.514011, 1.61581)),
+    "hb_small": HasenbuschWorkload(Workload("hb_small", 12, 12, 32, 1.0, 3.0, 8.0, seed=21), (0.514011, 1.61581)),
+    "hb_large": HasenbuschWorkload(Workload("hb_large", 102, 102, 64, 1.0, 3.8, 12.0, seed=22), (0.4054, 1.09624)),
+}
+
+
 def draw_phi(rng: np.random.Generator, w: Workload) -> np.ndarray:
     """phi ~ N(0, U~), float64 [N_t][2][L1][L2]."""
     return rng.normal(0.0, math.sqrt(w.U_t), size=w.shape)
@@ -113,6 +140,12 @@ def draw_inputs(w: Workload, seed: int | None = None, batch: int | None = None):
     nb = w.batch if batch is None else batch
     eta = np.stack([draw_gaussian_c128(rng, w.shape) for _ in range(nb)])
     return phi, eta
+
+
+def draw_hasenbusch(hw: HasenbuschWorkload, seed: int | None = None):
+    """Return (phi, rho) for a Hasenbusch workload: rho [n+1, N_t, 2, L1, L2] holds the
+    heat-bath vectors rho_0 .. rho_n (drawn phi first, then rho_0, rho_1, ...)."""
+    return draw_inputs(hw.base, seed=seed, batch=hw.nterms)
 
 
 def serving_stream(n: int, seed: int = 5, rate: float = 200.0,
