@@ -11,7 +11,11 @@ Printed JSON (one line): solves/s over the timed steps, the roofline of the
 dominant kernel (HIP events around its launches in the timed region), the M-apply
 bandwidth, the FP64 CG comparison, a short serving run and the CPU oracle baseline.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving]
+Further legs (not part of the step): the staggered-mass Hasenbusch split at the
+same lattice with the paper's tuned two masses (heat-bath, all-terms and per-term
+force evaluations).
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-hasenbusch]
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-from workloads import WORKLOADS, draw_inputs, serving_stream  # noqa: E402
+from workloads import HASENBUSCH, WORKLOADS, draw_hasenbusch, draw_inputs, serving_stream  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
 MALL_BYTES = 256 << 20   # infinity cache
@@ -45,6 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-hasenbusch", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     return ap.parse_args()
@@ -250,12 +255,81 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in prof.items()},
     }
 
+    if not args.no_hasenbusch:
+        out["hasenbusch"] = hasenbusch_run(ctx, hb, torch)
     if not args.no_serving:
         out["serving"] = serving_run(ctx, hb, torch, args.serving_requests)
     ctx.close()
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def hasenbusch_run(ctx, hb, torch, reps: int = 5) -> dict:
+    """Staggered-mass Hasenbusch split at 102x102, N_t = 64 with the paper's tuned masses
+    (mu_0, mu_1) = (0.4054, 1.09624): heat-bath of the three pseudofermions, then the
+    actions and summed force of all terms (three batched mixed-precision solves, 1e-10),
+    and each term alone; the plain single-term force on the same field for comparison."""
+    hw = HASENBUSCH["hb_large"]
+    w = hw.base
+    hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    phi, rho = draw_hasenbusch(hw)
+    pd = torch.from_numpy(phi).to("cuda")
+    rd = torch.from_numpy(rho).to("cuda")
+    opts = hb.default_opts(solver="fgmres", tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chi, hinfo, _ = hb.hub_hasenbusch_heatbath(ctx, hl, pd, hw.mts, rd, opts=opts)
+    torch.cuda.synchronize()
+    heat_ms = 1e3 * (time.perf_counter() - t0)
+    eta = torch.zeros_like(chi)
+    F = torch.zeros(pd.shape, dtype=torch.float64, device="cuda")
+
+    def run(terms):
+        return hb.hub_hasenbusch_force(ctx, hl, pd, hw.mts, chi, terms=terms, eta=eta, out=F, opts=opts)
+
+    S, infos = run(None)[1], run(None)[3]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run(None)
+    torch.cuda.synchronize()
+    all_ms = 1e3 * (time.perf_counter() - t0) / reps
+    per_term = []
+    for i in range(hw.nterms):
+        run([i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, _, inf, _ = run([i])
+        torch.cuda.synchronize()
+        per_term.append({"term": i, "ms": round(1e3 * (time.perf_counter() - t0) / reps, 3),
+                         "inner_iters": inf[i]["inner_iters"], "true_rel_resid": inf[i]["true_rel_resid"],
+                         "force_norm": round(float(torch.linalg.norm(F)), 4)})
+    r2 = [float(np.vdot(rho[i].ravel(), rho[i].ravel()).real) for i in range(hw.nterms)]
+    # the plain pseudofermion term (M with m_s = 0) on the same phi for comparison
+    chi0 = hb.hub_apply_M(ctx, hl, pd, rd[0:1])
+    x0 = torch.empty_like(chi0)
+    hb.hub_solve(ctx, hl, pd, [0.0], chi0, x=x0, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, inf0, _ = hb.hub_solve(ctx, hl, pd, [0.0], chi0, x=x0, opts=opts)
+        hb.hub_force(ctx, hl, pd, x0, out=F)
+    torch.cuda.synchronize()
+    plain_ms = 1e3 * (time.perf_counter() - t0) / reps
+    plain_norm = float(torch.linalg.norm(F))
+    return {"workload": "102x102 honeycomb, N_t=64, kappa=1, U=3.8, beta=12; staggered masses "
+                        f"{list(hw.masses)} (m~ = {[round(m, 6) for m in hw.mts]}); mixed FGMRES to 1e-10",
+            "terms": hw.nterms, "heatbath_ms": round(heat_ms, 3),
+            "heatbath_inner_iters": [i["inner_iters"] for i in hinfo],
+            "all_terms_force_ms": round(all_ms, 3),
+            "all_terms_per_s": round(1e3 / all_ms, 3),
+            "per_term": per_term,
+            "S_minus_rho2_rel": [abs(S[i] - r2[i]) / r2[i] for i in range(hw.nterms)],
+            "inner_iters": [infos[i]["inner_iters"] for i in range(hw.nterms)],
+            "plain_term_force_ms": round(plain_ms, 3), "plain_term_inner_iters": inf0[0]["inner_iters"],
+            "plain_force_norm": round(plain_norm, 4)}
 
 
 def serving_run(ctx, hb, torch, nreq: int) -> dict:

@@ -40,6 +40,7 @@ extern "C" {
 
 #define HUB_MAX_BATCH 64     /* systems per hub_apply_* / hub_solve / hub_force call */
 #define HUB_MAX_RESTART 20   /* largest FGMRES restart length m                      */
+#define HUB_MAX_HB_MASSES 16 /* staggered Hasenbusch masses per hub_hasenbusch_* call */
 
 typedef struct { double re, im; } hub_c128;
 
@@ -150,6 +151,45 @@ hub_status hub_force(hub_ctx *ctx, const hub_lattice *lat, const double *phi, co
  * chi, eta: device [batch][N]; S: host float64 [batch].  Synchronises `stream`. */
 hub_status hub_action(hub_ctx *ctx, const hub_lattice *lat, const hub_c128 *chi, const hub_c128 *eta,
                       int32_t batch, double *S, hipStream_t stream);
+
+/* Staggered-mass Hasenbusch split (Sec. 5.1).  The pseudofermion term is replaced by
+ * n+1 terms built from M_i = M(m_s = mu_i), i = 0..n-1, with M_{-1} = M(lat->ms_t)
+ * (the paper's M, m_s = 0).  mt: host [n], the staggered masses as m~_i = delta*mu_i
+ * (the convention of hub_lattice.ms_t), 1 <= n <= HUB_MAX_HB_MASSES.  Term i of
+ * pseudofermion chi_i (device [n+1][N], term order 0..n):
+ *   term n   : S_n = chi_n^dag (M_{n-1} M_{n-1}^dag)^{-1} chi_n
+ *   term i<n : S_i = (M_i chi_i)^dag (M_{i-1} M_{i-1}^dag)^{-1} (M_i chi_i)
+ *
+ * Heat-bath: chi_n = M_{n-1} rho_n and chi_i = M_i^{-1} M_{i-1} rho_i
+ * = M_i^dag (M_i M_i^dag)^{-1} M_{i-1} rho_i for i < n, so that S_i = rho_i^dag rho_i.
+ * rho: device [n+1][N], drawn by the caller with density e^{-rho^dag rho}.  The n
+ * solves run as one batch.  info: host [n] (solve i).  opts may be NULL; use_x0 is
+ * ignored.  Synchronises `stream`.  HUB_ERR_NOCONV if a solve missed tol (chi is
+ * still written from its last iterate). */
+hub_status hub_hasenbusch_heatbath(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mt,
+                                   int32_t n, const hub_c128 *rho, hub_c128 *chi, const hub_solve_opts *opts,
+                                   hub_solve_info *info, hipStream_t stream);
+
+/* Actions and summed force of the terms selected by term_mask (bit i = term i, at
+ * least one bit, none above bit n), for multi-time-scale integration where terms
+ * are evaluated at different rates (Sec. 5.2).  For each selected term the solve
+ *   (M_d M_d^dag) eta_i = rhs_i,  d = n-1 for term n and i-1 for i < n,
+ *   rhs_n = chi_n, rhs_i = M_i chi_i,
+ * runs in one batch with the others; then xi_i = M_d^dag eta_i (eq. (def_xi_i)),
+ * S_i = Re rhs_i^dag eta_i, and
+ *   dSdphi (+)= scale * sum_i dS_i/dphi,
+ *   dS_n/dphi = -2 Re(eta_n^dag dM/dphi xi_n),
+ *   dS_i/dphi = -2 Re(eta_i^dag dM/dphi (xi_i - chi_i))   (minus eq. (f_chi_i)),
+ * the same contraction as hub_force.  eta: device [n+1][N], in/out: the selected
+ * terms' solutions are written there (and read as initial guesses iff
+ * opts->use_x0); other terms are untouched.  S: host [n+1] or NULL; info: host
+ * [n+1]; only selected entries are written.  accumulate = 0 overwrites dSdphi
+ * (device float64 [N]), 1 adds to it.  Synchronises `stream`.  HUB_ERR_NOCONV if a
+ * solve missed tol (the outputs are still computed from its last iterate). */
+hub_status hub_hasenbusch_force(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mt,
+                                int32_t n, const hub_c128 *chi, uint32_t term_mask, double scale,
+                                int32_t accumulate, double *dSdphi, double *S, hub_c128 *eta,
+                                const hub_solve_opts *opts, hub_solve_info *info, hipStream_t stream);
 
 /* Serving: one request = solve (M M^dagger + mu2) x = chi, then S = Re chi^dagger x and
  * dS/dphi, for its own lattice, phi and shift.  Requests are admitted by workspace

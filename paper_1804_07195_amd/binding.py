@@ -21,12 +21,13 @@ HUB_OK, HUB_ERR_ARG, HUB_ERR_OOM, HUB_ERR_NOCONV, HUB_ERR_HIP, HUB_ERR_BUSY, HUB
 HUB_CG_FP64, HUB_FGMRES_MIXED = 0, 1
 HUB_MAX_BATCH = 64
 HUB_MAX_RESTART = 20
+HUB_MAX_HB_MASSES = 16
 STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOCONV", 4: "HUB_ERR_HIP",
                 5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
 
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
            "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
-           "hub_profile_enable", "hub_profile_read"]
+           "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force"]
 
 
 class HubLattice(ctypes.Structure):
@@ -92,6 +93,11 @@ def load() -> ctypes.CDLL:
     L.hub_action.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.hub_submit.argtypes = [vp, ctypes.POINTER(HubRequest), ctypes.POINTER(ctypes.c_uint64)]
     L.hub_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(HubSolveInfo)]
+    L.hub_hasenbusch_heatbath.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
+                                          ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
+    L.hub_hasenbusch_force.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp,
+                                       ctypes.c_uint32, dbl, i32, vp, ctypes.POINTER(dbl), vp,
+                                       ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
     L.hub_profile_enable.argtypes = [vp, i32]
     L.hub_profile_read.argtypes = [vp, ctypes.POINTER(HubKernelStat), i32, ctypes.POINTER(i32)]
     for name in SYMBOLS:
@@ -247,6 +253,63 @@ def hub_action(ctx: Context, lat: HubLattice, chi, eta, stream=None):
     _check(load().hub_action(ctx.handle, ctypes.byref(lat), chi.data_ptr(), eta.data_ptr(), nb, S,
                              _stream(stream)))
     return list(S)
+
+
+def hub_hasenbusch_heatbath(ctx: Context, lat: HubLattice, phi, mts, rho, chi=None,
+                            opts: HubSolveOpts | None = None, stream=None, allow_noconv: bool = False):
+    """Pseudofermions chi_0..chi_n of the staggered-mass Hasenbusch split from rho_0..rho_n
+    (device complex128 [n+1, N_t, 2, L1, L2]); mts = [m~_0, ..., m~_{n-1}].
+    Returns (chi, [info dicts of the n solves], status)."""
+    _phi(phi, lat)
+    n = len(mts)
+    if _vec(rho, lat, "rho") != n + 1:
+        raise ValueError("rho must hold n+1 vectors")
+    if chi is None:
+        chi = torch.empty_like(rho)
+    if _vec(chi, lat, "chi") != n + 1:
+        raise ValueError("chi must hold n+1 vectors")
+    m = (ctypes.c_double * n)(*[float(v) for v in mts])
+    o = default_opts() if opts is None else opts
+    info = (HubSolveInfo * n)()
+    st = load().hub_hasenbusch_heatbath(ctx.handle, ctypes.byref(lat), phi.data_ptr(), m, n, rho.data_ptr(),
+                                        chi.data_ptr(), ctypes.byref(o), info, _stream(stream))
+    _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
+    return chi, [i.as_dict() for i in info], st
+
+
+def hub_hasenbusch_force(ctx: Context, lat: HubLattice, phi, mts, chi, terms=None, eta=None, scale: float = 1.0,
+                         accumulate: bool = False, out=None, opts: HubSolveOpts | None = None, stream=None,
+                         allow_noconv: bool = False):
+    """Summed dS_i/dphi over `terms` (default all n+1) of the staggered-mass Hasenbusch split.
+    Returns (dSdphi [N_t, 2, L1, L2], S list [n+1] (None for terms not evaluated),
+    eta [n+1, ...], info list, status)."""
+    _phi(phi, lat)
+    n = len(mts)
+    if _vec(chi, lat, "chi") != n + 1:
+        raise ValueError("chi must hold n+1 vectors")
+    terms = list(range(n + 1)) if terms is None else sorted(set(int(t) for t in terms))
+    mask = 0
+    for t in terms:
+        mask |= 1 << t
+    if eta is None:
+        eta = torch.zeros_like(chi)
+    if _vec(eta, lat, "eta") != n + 1:
+        raise ValueError("eta must hold n+1 vectors")
+    if out is None:
+        out = torch.zeros(chi.shape[1:], dtype=torch.float64, device=chi.device)
+    if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != _nsites(lat):
+        raise ValueError("out must be a contiguous float64 tensor with N entries")
+    m = (ctypes.c_double * n)(*[float(v) for v in mts])
+    S = (ctypes.c_double * (n + 1))(*([float("nan")] * (n + 1)))
+    o = default_opts() if opts is None else opts
+    info = (HubSolveInfo * (n + 1))()
+    st = load().hub_hasenbusch_force(ctx.handle, ctypes.byref(lat), phi.data_ptr(), m, n, chi.data_ptr(),
+                                     ctypes.c_uint32(mask), float(scale), 1 if accumulate else 0, out.data_ptr(),
+                                     S, eta.data_ptr(), ctypes.byref(o), info, _stream(stream))
+    _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
+    Sl = [S[i] if i in terms else None for i in range(n + 1)]
+    il = [info[i].as_dict() if i in terms else None for i in range(n + 1)]
+    return out, Sl, eta, il, st
 
 
 class Pending:

@@ -346,6 +346,60 @@ hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* 
   return HUB_OK;
 }
 
+namespace {
+
+// Solves the prepared systems (each with its own geometry, shift, right-hand side
+// and solution buffer; one phi) on the stream's engine, then synchronises the
+// stream.  The caller holds ctx->mu and has set the device.  Per-system results are
+// in sys[k].info and sys[k].status; the return value is the first failure
+// (HUB_ERR_NOCONV if a system stopped at its iteration limit).
+hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const double* phi, const hub_solve_opts& o,
+                      hipStream_t stream) {
+  Engine* eng = engine_for(ctx, stream);
+  const int n = sys.empty() ? 0 : sys[0].g.n;
+  float* phi32 = nullptr;
+  if (o.solver == HUB_FGMRES_MIXED) {
+    phi32 = (float*)ctx->pool->alloc((size_t)n * 4, stream);
+    if (!phi32) return fail(HUB_ERR_OOM, "workspace for phi in single precision");
+    HUB_HIP(launch_phi_to_f32(phi, phi32, n, stream), "phi conversion");
+  }
+  hub_status result = HUB_OK;
+  size_t added = 0;
+  for (System& sy : sys) {
+    sy.phi = phi;
+    sy.phi32 = phi32;
+    sy.opts = o;
+    if (!eng->add(&sy)) {
+      result = fail(HUB_ERR_OOM, "solver workspace");
+      break;
+    }
+    ++added;
+  }
+  if (result == HUB_OK) {
+    for (;;) {
+      hipError_t e = eng->step();
+      if (e != hipSuccess) {
+        result = hip_fail(e, "solve");
+        break;
+      }
+      bool all = true;
+      for (const System& sy : sys) all = all && sy.done;
+      if (all) break;
+    }
+  }
+  for (size_t k = 0; k < added; ++k) eng->remove(&sys[k]);
+  if (phi32) ctx->pool->release(phi32, stream);
+  hipError_t e = hipStreamSynchronize(stream);
+  if (result != HUB_OK) return result;
+  if (e != hipSuccess) return hip_fail(e, "solve");
+  for (const System& sy : sys)
+    if (sy.status != HUB_OK && result == HUB_OK) result = sy.status;
+  if (result == HUB_ERR_NOCONV) set_error("iteration limit reached before the tolerance");
+  return result;
+}
+
+}  // namespace
+
 hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2, int32_t batch,
                      const hub_c128* b, hub_c128* x, const hub_solve_opts* opts, hub_solve_info* info,
                      hipStream_t stream) {
@@ -364,53 +418,16 @@ hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   std::lock_guard<std::mutex> lk(ctx->mu);
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
-  Engine* eng = engine_for(ctx, stream);
-  float* phi32 = nullptr;
-  if (o.solver == HUB_FGMRES_MIXED) {
-    phi32 = (float*)ctx->pool->alloc((size_t)g.n * 4, stream);
-    if (!phi32) return HUB_ERR_OOM;
-    HUB_HIP(launch_phi_to_f32(phi, phi32, g.n, stream), "phi conversion");
-  }
   std::vector<System> sys((size_t)batch);
-  hub_status result = HUB_OK;
-  int added = 0;
   for (int k = 0; k < batch; ++k) {
-    System& sy = sys[k];
-    sy.g = g;
-    sy.mu2 = mu2[k];
-    sy.phi = phi;
-    sy.phi32 = phi32;
-    sy.b = (const double2*)(b + (size_t)k * g.n);
-    sy.x = (double2*)(x + (size_t)k * g.n);
-    sy.opts = o;
-    if (!eng->add(&sy)) {
-      result = HUB_ERR_OOM;
-      break;
-    }
-    ++added;
+    sys[k].g = g;
+    sys[k].mu2 = mu2[k];
+    sys[k].b = (const double2*)(b + (size_t)k * g.n);
+    sys[k].x = (double2*)(x + (size_t)k * g.n);
   }
-  if (result == HUB_OK) {
-    for (;;) {
-      hipError_t e = eng->step();
-      if (e != hipSuccess) {
-        result = hip_fail(e, "solve");
-        break;
-      }
-      bool all = true;
-      for (int k = 0; k < batch; ++k) all = all && sys[k].done;
-      if (all) break;
-    }
-  }
-  for (int k = 0; k < added; ++k) eng->remove(&sys[k]);
-  if (phi32) ctx->pool->release(phi32, stream);
-  hipError_t e = hipStreamSynchronize(stream);
-  if (result != HUB_OK) return result;
-  if (e != hipSuccess) return hip_fail(e, "solve");
-  for (int k = 0; k < batch; ++k) {
-    info[k] = sys[k].info;
-    if (sys[k].status != HUB_OK && result == HUB_OK) result = sys[k].status;
-  }
-  if (result == HUB_ERR_NOCONV) set_error("iteration limit reached before the tolerance");
+  const hub_status result = run_solves(ctx, sys, phi, o, stream);
+  if (result != HUB_OK && result != HUB_ERR_NOCONV) return result;
+  for (int k = 0; k < batch; ++k) info[k] = sys[k].info;
   return result;
 }
 
@@ -467,6 +484,155 @@ hub_status hub_action(hub_ctx* ctx, const hub_lattice* lat, const hub_c128* chi,
   ctx->pool->release(ws, stream);
   if (e != hipSuccess) return hip_fail(e, "action");
   return HUB_OK;
+}
+
+namespace {
+
+hub_status check_masses(const double* mt, int32_t n) {
+  if (!mt) return fail(HUB_ERR_ARG, "masses is NULL");
+  if (n < 1 || n > HUB_MAX_HB_MASSES) return fail(HUB_ERR_ARG, "n must be in [1, HUB_MAX_HB_MASSES]");
+  for (int i = 0; i < n; ++i)
+    if (!is_finite(mt[i])) return fail(HUB_ERR_ARG, "masses must be finite");
+  return HUB_OK;
+}
+
+// Geometry of M_{mu_i}; i = -1 is the lattice's own operator.
+Geom geom_with_mass(const hub_lattice& lat, const double* mt, int i) {
+  hub_lattice l = lat;
+  if (i >= 0) l.ms_t = mt[i];
+  return make_geom(l);
+}
+
+}  // namespace
+
+hub_status hub_hasenbusch_heatbath(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mt,
+                                   int32_t n, const hub_c128* rho, hub_c128* chi, const hub_solve_opts* opts,
+                                   hub_solve_info* info, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_masses(mt, n))) return s;
+  if (!phi || !rho || !chi || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  if ((const void*)rho == (const void*)chi) return fail(HUB_ERR_ARG, "rho and chi must not overlap");
+  hub_solve_opts o;
+  hub_default_opts(&o);
+  if (opts) o = *opts;
+  o.use_x0 = 0;
+  if ((s = check_opts(o))) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const size_t N = (size_t)make_geom(*lat).n;
+  const double2* r = (const double2*)rho;
+  double2* c = (double2*)chi;
+  // chi_n = M_{n-1} rho_n
+  HUB_HIP(launch_apply(geom_with_mass(*lat, mt, n - 1), phi, r + n * N, c + n * N, 1, false, stream), "apply");
+  // chi_i = M_i^{-1} M_{i-1} rho_i = M_i^dag (M_i M_i^dag)^{-1} M_{i-1} rho_i, i < n
+  double2* w = (double2*)ctx->pool->alloc(2 * (size_t)n * N * 16, stream);
+  if (!w) return fail(HUB_ERR_OOM, "heat-bath workspace");
+  double2* y = w + (size_t)n * N;
+  std::vector<System> sys((size_t)n);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = launch_apply(geom_with_mass(*lat, mt, i - 1), phi, r + i * N, w + i * N, 1, false, stream);
+    sys[i].g = geom_with_mass(*lat, mt, i);
+    sys[i].mu2 = 0.0;
+    sys[i].b = w + i * N;
+    sys[i].x = y + i * N;
+  }
+  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, o, stream) : hip_fail(e, "apply");
+  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+      e = launch_apply(sys[i].g, phi, y + i * N, c + i * N, 1, true, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) result = hip_fail(e, "apply");
+    for (int i = 0; i < n; ++i) info[i] = sys[i].info;
+  }
+  ctx->pool->release(w, stream);
+  return result;
+}
+
+hub_status hub_hasenbusch_force(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mt,
+                                int32_t n, const hub_c128* chi, uint32_t term_mask, double scale,
+                                int32_t accumulate, double* dSdphi, double* S, hub_c128* eta,
+                                const hub_solve_opts* opts, hub_solve_info* info, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_masses(mt, n))) return s;
+  if (!phi || !chi || !dSdphi || !eta || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  if ((const void*)chi == (const void*)eta) return fail(HUB_ERR_ARG, "chi and eta must not overlap");
+  if (term_mask == 0 || (n < 31 && (term_mask >> (n + 1)) != 0))
+    return fail(HUB_ERR_ARG, "term_mask must select terms in [0, n]");
+  if (!is_finite(scale)) return fail(HUB_ERR_ARG, "scale must be finite");
+  if (accumulate != 0 && accumulate != 1) return fail(HUB_ERR_ARG, "accumulate must be 0 or 1");
+  hub_solve_opts o;
+  hub_default_opts(&o);
+  if (opts) o = *opts;
+  if ((s = check_opts(o))) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const Geom g = make_geom(*lat);
+  const size_t N = (size_t)g.n;
+  std::vector<int> terms;
+  for (int i = 0; i <= n; ++i)
+    if (term_mask & (1u << i)) terms.push_back(i);
+  const int T = (int)terms.size();
+  const int nt = ntiles_of(g.n);
+  // workspace: M_i chi_i for the ratio terms, xi per term, dot partials and results
+  const size_t vec_bytes = (size_t)T * N * 16;
+  const size_t part_bytes = (size_t)T * nt * sizeof(double);
+  char* ws = (char*)ctx->pool->alloc(2 * vec_bytes + part_bytes + 64 * sizeof(double), stream);
+  if (!ws) return fail(HUB_ERR_OOM, "Hasenbusch workspace");
+  double2* wv = (double2*)ws;
+  double2* xv = (double2*)(ws + vec_bytes);
+  double* part = (double*)(ws + 2 * vec_bytes);
+  double* res = (double*)(ws + 2 * vec_bytes + part_bytes);
+  const double2* c = (const double2*)chi;
+  double2* et = (double2*)eta;
+  std::vector<System> sys((size_t)T);
+  std::vector<const double2*> rhs((size_t)T);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < T && e == hipSuccess; ++k) {
+    const int i = terms[k];
+    const int den = i == n ? n - 1 : i - 1;
+    if (i == n) {
+      rhs[k] = c + i * N;
+    } else {
+      e = launch_apply(geom_with_mass(*lat, mt, i), phi, c + i * N, wv + k * N, 1, false, stream);
+      rhs[k] = wv + k * N;
+    }
+    sys[k].g = geom_with_mass(*lat, mt, den);
+    sys[k].mu2 = 0.0;
+    sys[k].b = rhs[k];
+    sys[k].x = et + i * N;
+  }
+  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, o, stream) : hip_fail(e, "apply");
+  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
+    double Sh[64] = {0};
+    for (int k = 0; k < T && e == hipSuccess; ++k) {
+      const int i = terms[k];
+      // S_i = Re rhs_i^dag eta_i; xi_i = M_den^dag eta_i; dS_i/dphi with xi_i (- chi_i)
+      e = launch_dot_re(g, rhs[k], et + i * N, 1, part + (size_t)k * nt, res + k, stream);
+      if (e == hipSuccess) e = launch_apply(sys[k].g, phi, et + i * N, xv + k * N, 1, true, stream);
+      if (e == hipSuccess)
+        e = launch_force(g, phi, et + i * N, xv + k * N, scale, (k == 0) ? accumulate : 1, dSdphi, 1, stream,
+                         i == n ? nullptr : c + i * N);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(Sh, res, T * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      result = hip_fail(e, "Hasenbusch force");
+    } else {
+      for (int k = 0; k < T; ++k) {
+        if (S) S[terms[k]] = Sh[k];
+        info[terms[k]] = sys[k].info;
+      }
+    }
+  }
+  ctx->pool->release(ws, stream);
+  return result;
 }
 
 hub_status hub_submit(hub_ctx* ctx, const hub_request* req, uint64_t* ticket) {

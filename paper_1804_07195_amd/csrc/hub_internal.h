@@ -126,8 +126,10 @@ hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, doub
                         bool dag, hipStream_t st);
 hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
                           const double2* x, double2* y, int batch, hipStream_t st);
+// out (+)= scale dS/dphi for eta and xi (minus `sub` when given: Hasenbusch ratio terms).
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi,
-                        double scale, int accumulate, double* out, int batch, hipStream_t st);
+                        double scale, int accumulate, double* out, int batch, hipStream_t st,
+                        const double2* sub = nullptr);
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
                          double* result, hipStream_t st);
 hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st);

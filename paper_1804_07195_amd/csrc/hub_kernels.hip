@@ -473,11 +473,14 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
   stencil_sites<double, false, kPubSites, kPubSites>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
 }
 
-// dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} xi(t-1)],
-//                        B: 2 Im[conj(eta(t)) s e^{-i phi} xi(t+1)].
+// dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} z(t-1)],
+//                        B: 2 Im[conj(eta(t)) s e^{-i phi} z(t+1)],
+// with z = xi, or z = xi - sub for the ratio terms of the Hasenbusch split
+// (eq. (f_chi_i)); the derivative of M does not depend on the staggered mass.
 __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restrict__ phi,
                                                   const double2* __restrict__ eta,
-                                                  const double2* __restrict__ xi, double scale, int accumulate,
+                                                  const double2* __restrict__ xi,
+                                                  const double2* __restrict__ sub, double scale, int accumulate,
                                                   double* __restrict__ out, int ntiles) {
   const int l = xcd_remap(blockIdx.x, gridDim.x);
   const int b = l / ntiles, tile = l - b * ntiles;
@@ -505,7 +508,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restri
       double c, s;
       sincos(phi[n], &s, &c);
       if (!isA) s = -s;
-      const double2 e = eta[off + n], z = xi[off + tn];
+      const double2 e = eta[off + n];
+      double2 z = xi[off + tn];
+      if (sub) {
+        const double2 v = sub[off + tn];
+        z.x -= v.x;
+        z.y -= v.y;
+      }
       // w = sgn (c + i s) z ; F = 2 Im(conj(e) w)
       const double wr = sgn * (c * z.x - s * z.y), wi = sgn * (c * z.y + s * z.x);
       const double F = 2.0 * (e.x * wi - e.y * wr);
@@ -1023,9 +1032,10 @@ hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_hos
 }
 
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi, double scale,
-                        int accumulate, double* out, int batch, hipStream_t st) {
+                        int accumulate, double* out, int batch, hipStream_t st, const double2* sub) {
   const int nt = tiles_of(g.n);
-  hipLaunchKernelGGL(k_force, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, eta, xi, scale, accumulate, out, nt);
+  hipLaunchKernelGGL(k_force, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, eta, xi, sub, scale, accumulate, out,
+                     nt);
   return hipGetLastError();
 }
 

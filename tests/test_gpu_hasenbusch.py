@@ -1,0 +1,163 @@
+"""GPU parity of the staggered-mass Hasenbusch split (Sec. 5.1) through the C ABI.
+
+Bars (FP64 results):
+* heat-bath chi and the per-term solutions eta against the oracle: 2-norm relative
+  error <= 1e-8 with the solves at tol 1e-12 (error <= cond * residual);
+* actions: relative error <= 1e-9 against the oracle; at the heat-bath point every
+  term equals rho_i^dag rho_i (an exact property at any size) to 1e-9;
+* summed force: 2-norm relative error <= 1e-8 against the oracle (solves at 1e-12);
+  at the paper's full 102x102, N_t = 64 shape the force is checked against the
+  oracle's contraction of the GPU's own eta, and eta by its oracle true residual;
+* mu_i = mu_{i-1}: the ratio term's force vanishes up to the solve tolerance;
+* terms evaluated one at a time with accumulation equal the all-terms call bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import hasenbusch as ohb
+from paper_1804_07195_amd import binding as hb
+from tests.gpu_helpers import dev, host, rel2
+from workloads import HASENBUSCH, draw_hasenbusch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hub():
+    ctx = hb.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _setup(name):
+    hw = HASENBUSCH[name]
+    w = hw.base
+    hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    ol = oracle.Lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    phi, rho = draw_hasenbusch(hw)
+    return hw, hl, ol, phi, rho
+
+
+@pytest.mark.parametrize("name", ["hb_tiny", "hb_small"])
+@pytest.mark.parametrize("solver", ["cg", "fgmres"])
+def test_heatbath_actions_and_force_match_oracle(hub, name, solver):
+    hw, hl, ol, phi, rho = _setup(name)
+    opts = hb.default_opts(solver=solver, tol=1e-12)
+    pd = dev(phi)
+    chi, infos, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, hw.mts, dev(rho), opts=opts)
+    assert all(i["converged"] == 1 for i in infos)
+    chi_o = ohb.heatbath(ol, phi, hw.mts, rho)
+    chi_h = host(chi)
+    for i in range(hw.nterms):
+        assert rel2(chi_h[i], chi_o[i]) <= 1e-8, i
+    F, S, eta, infos, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi, opts=opts)
+    assert all(i["converged"] == 1 for i in infos)
+    S_o, F_o = ohb.actions_and_forces(ol, phi, hw.mts, chi_h)
+    for i in range(hw.nterms):
+        r2 = float(np.vdot(rho[i].ravel(), rho[i].ravel()).real)
+        assert abs(S[i] - S_o[i]) <= 1e-9 * abs(S_o[i]), (i, S[i], S_o[i])
+        assert abs(S[i] - r2) <= 1e-9 * r2, (i, S[i], r2)
+    assert rel2(host(F), F_o) <= 1e-8
+    # per-term solutions
+    eta_h = host(eta)
+    for i in range(hw.nterms):
+        _, _, eta_o, _ = ohb.term(ol, phi, hw.mts, chi_h[i], i)
+        assert rel2(eta_h[i], eta_o) <= 1e-8, i
+
+
+def test_terms_one_at_a_time_equal_all_terms(hub):
+    hw, hl, ol, phi, rho = _setup("hb_small")
+    pd = dev(phi)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, hw.mts, dev(rho))
+    F_all, S_all, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi)
+    F = torch.zeros_like(F_all)
+    for i in range(hw.nterms):
+        _, S, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi, terms=[i], out=F, accumulate=True)
+        assert S[i] == S_all[i]
+        assert all(S[k] is None for k in range(hw.nterms) if k != i)
+    assert torch.equal(F, F_all)
+
+
+def test_scale_and_accumulate(hub):
+    hw, hl, ol, phi, rho = _setup("hb_tiny")
+    pd = dev(phi)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, hw.mts, dev(rho))
+    F1, _, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi, terms=[0, 2])
+    base = torch.full_like(F1, 0.5)
+    F2, _, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi, terms=[0, 2], scale=-2.0,
+                                             accumulate=True, out=base.clone())
+    assert torch.allclose(F2, 0.5 - 2.0 * F1, rtol=0, atol=1e-13)
+
+
+def test_equal_masses_ratio_force_vanishes(hub):
+    hw, hl, ol, phi, rho = _setup("hb_small")
+    mts = [hw.mts[0], hw.mts[0]]
+    pd = dev(phi)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, mts, dev(rho))
+    F1, S, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, mts, chi, terms=[1])
+    F0, _, _, _, _ = hb.hub_hasenbusch_force(hub, hl, pd, mts, chi, terms=[0])
+    n1 = float(torch.linalg.norm(F1))
+    n0 = float(torch.linalg.norm(F0))
+    assert n0 > 1.0
+    assert n1 <= 1e-8 * n0
+    c1 = host(chi)[1]
+    assert abs(S[1] - np.vdot(c1.ravel(), c1.ravel()).real) <= 1e-9 * S[1]
+
+
+def test_full_size_hasenbusch(hub):
+    hw, hl, ol, phi, rho = _setup("hb_large")
+    pd = dev(phi)
+    opts = hb.default_opts(solver="fgmres")
+    chi, hinfo, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, hw.mts, dev(rho), opts=opts)
+    assert all(i["converged"] == 1 for i in hinfo)
+    F, S, eta, infos, _ = hb.hub_hasenbusch_force(hub, hl, pd, hw.mts, chi, opts=opts)
+    assert all(i["converged"] == 1 for i in infos)
+    chi_h, eta_h, F_h = host(chi), host(eta), host(F)
+    n = hw.nterms - 1
+    # lattices and sparse matrices of M_{-1} (base), M_0, .., M_{n-1}, built once
+    lats = [ol] + [ohb.lattice_with_mass(ol, m) for m in hw.mts]
+    Ms = [oracle.build_M(l, phi) for l in lats]
+    F_o = np.zeros(ol.shape)
+    for i in range(n + 1):
+        r2 = float(np.vdot(rho[i].ravel(), rho[i].ravel()).real)
+        assert abs(S[i] - r2) <= 1e-9 * r2, (i, S[i], r2)
+        d = n if i == n else i  # index into lats of the solve's operator M_{den}
+        if i < n:
+            # heat-bath defining equation M_i chi_i = M_{i-1} rho_i
+            lhs = oracle.apply_M(lats[i + 1], phi, chi_h[i], M=Ms[i + 1])
+            rhs = oracle.apply_M(lats[i], phi, rho[i], M=Ms[i])
+            assert rel2(lhs, rhs) <= 1e-9, i
+            w = lhs
+        else:
+            w = chi_h[i]
+        # eta: oracle true residual of its system; force: oracle contraction of the GPU's eta
+        A = oracle.operator.NormalOperator(lats[d], phi, 0.0, M=Ms[d])
+        assert oracle.true_rel_residual(lats[d], phi, 0.0, w, eta_h[i], A=A) <= 1e-10, i
+        xi = oracle.apply_Mdag(lats[d], phi, eta_h[i], M=Ms[d])
+        F_o += oracle.force(lats[d], phi, eta_h[i], xi if i == n else xi - chi_h[i])
+    assert rel2(F_h, F_o) <= 1e-11
+
+
+def test_argument_errors(hub):
+    hw, hl, ol, phi, rho = _setup("hb_tiny")
+    pd, rd = dev(phi), dev(rho)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, hw.mts, rd)
+    L = hb.load()
+    import ctypes
+    m = (ctypes.c_double * 2)(*hw.mts)
+    info = (hb.HubSolveInfo * 3)()
+    out = torch.zeros(ol.shape, dtype=torch.float64, device="cuda")
+    eta = torch.zeros_like(chi)
+    args = lambda n, mask: (hub.handle, ctypes.byref(hl), pd.data_ptr(), m, n, chi.data_ptr(), ctypes.c_uint32(mask),
+                            1.0, 0, out.data_ptr(), None, eta.data_ptr(), None, info, None)
+    assert L.hub_hasenbusch_force(*args(2, 0)) == hb.HUB_ERR_ARG          # no term
+    assert L.hub_hasenbusch_force(*args(2, 1 << 3)) == hb.HUB_ERR_ARG     # term beyond n
+    assert L.hub_hasenbusch_force(*args(0, 1)) == hb.HUB_ERR_ARG          # n < 1
+    assert L.hub_hasenbusch_force(*args(17, 1)) == hb.HUB_ERR_ARG         # n > HUB_MAX_HB_MASSES
+    assert L.hub_hasenbusch_heatbath(hub.handle, ctypes.byref(hl), pd.data_ptr(), m, 2, rd.data_ptr(),
+                                     rd.data_ptr(), None, info, None) == hb.HUB_ERR_ARG  # rho == chi
+    nan = (ctypes.c_double * 2)(float("nan"), 0.1)
+    assert L.hub_hasenbusch_heatbath(hub.handle, ctypes.byref(hl), pd.data_ptr(), nan, 2, rd.data_ptr(),
+                                     chi.data_ptr(), None, info, None) == hb.HUB_ERR_ARG
