@@ -21,19 +21,21 @@ complex128 / float64 with NumPy and SciPy sparse matrices:
                 (eta_xi), contracting the explicit derivative of M;
 * `hasenbusch` - the staggered-mass Hasenbusch split of Sec. 5.1: heat-bath of the
                 n+1 pseudofermions, the per-term actions and the ratio forces of
-                eq. (f_chi_i).
+                eq. (f_chi_i);
+* `hmc`       - the HMC update of Sec. 2 with the nested second-order Omelyan
+                integrator of Sec. 5.2 and the Metropolis step.
 
 Every function is pinned by a test in `tests/test_oracle_pins.py` or
-`tests/test_oracle_hasenbusch.py` against a
+`tests/test_oracle_hasenbusch.py` / `tests/test_oracle_hmc.py` against a
 closed form, an invariance or brute force that does not reuse its code.
 """
 from .operator import Lattice, build_M, build_M_dense_loops, apply_M, apply_Mdag, normal_apply, site_index
 from .solve import solve, solve_dense, cg, true_rel_residual, fgmres_alg_a1
 from .force import action, force, xi_from_eta
-from . import hasenbusch
+from . import hasenbusch, hmc
 
 __all__ = [
     "Lattice", "build_M", "build_M_dense_loops", "apply_M", "apply_Mdag", "normal_apply", "site_index",
     "solve", "solve_dense", "cg", "true_rel_residual", "fgmres_alg_a1",
-    "action", "force", "xi_from_eta", "hasenbusch",
+    "action", "force", "xi_from_eta", "hasenbusch", "hmc",
 ]
