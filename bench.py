@@ -13,9 +13,10 @@ bandwidth, the FP64 CG comparison, a short serving run and the CPU oracle baseli
 
 Further legs (not part of the step): the staggered-mass Hasenbusch split at the
 same lattice with the paper's tuned two masses (heat-bath, all-terms and per-term
-force evaluations).
+force evaluations), and one full HMC trajectory with the paper's nested Omelyan
+schedule for that lattice.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-hasenbusch]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-hasenbusch] [--no-hmc]
 """
 from __future__ import annotations
 
@@ -34,7 +35,8 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-from workloads import HASENBUSCH, WORKLOADS, draw_hasenbusch, draw_inputs, serving_stream  # noqa: E402
+from workloads import (HASENBUSCH, WORKLOADS, draw_hasenbusch, draw_hmc, draw_inputs,  # noqa: E402
+                       serving_stream)
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
 MALL_BYTES = 256 << 20   # infinity cache
@@ -50,6 +52,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-hasenbusch", action="store_true")
+    ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     return ap.parse_args()
@@ -257,6 +260,8 @@ def main():
 
     if not args.no_hasenbusch:
         out["hasenbusch"] = hasenbusch_run(ctx, hb, torch)
+    if not args.no_hmc:
+        out["hmc"] = hmc_run(ctx, hb, torch)
     if not args.no_serving:
         out["serving"] = serving_run(ctx, hb, torch, args.serving_requests)
     ctx.close()
@@ -330,6 +335,32 @@ def hasenbusch_run(ctx, hb, torch, reps: int = 5) -> dict:
             "inner_iters": [infos[i]["inner_iters"] for i in range(hw.nterms)],
             "plain_term_force_ms": round(plain_ms, 3), "plain_term_inner_iters": inf0[0]["inner_iters"],
             "plain_force_norm": round(plain_norm, 4)}
+
+
+def hmc_run(ctx, hb, torch) -> dict:
+    """One HMC update at 102x102, N_t = 64 with the paper's tuned Hasenbusch schedule for
+    that lattice (Table tab_nmds: N_MD = 30, N_MD / N_0 = 15, so N_0 = N_1 = 2), trajectory
+    length 1, Omelyan zeta = 0.1931833, mixed FGMRES solves to 1e-10 with warm starts."""
+    hw = HASENBUSCH["hb_large"]
+    w = hw.base
+    hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    phi, pi, rho = draw_hmc(hw)
+    pd = torch.from_numpy(phi).to("cuda")
+    qd = torch.from_numpy(pi).to("cuda")
+    rd = torch.from_numpy(rho).to("cuda")
+    p = hb.hmc_params(w.U_t, 30, hw.mts, [2, 2], traj_length=1.0)
+    opts = hb.default_opts(solver="fgmres", tol=1e-10)
+    opts.use_x0 = 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = hb.hub_hmc_trajectory(ctx, hl, pd, qd, rd, 0.5, p, opts=opts)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return {"workload": "102x102 honeycomb, N_t=64, kappa=1, U=3.8, beta=12; Hasenbusch masses "
+                        f"{list(hw.masses)}; N_MD=30, N_0=N_1=2, t=1, zeta=0.1931833; hot start phi ~ N(0, U~)",
+            "seconds_per_trajectory": round(sec, 3), "dH": info["dH"], "accepted_at_u_0.5": info["accepted"],
+            "force_evals_per_term": info["force_evals"], "kick_groups": info["kick_groups"],
+            "drifts": info["drifts"], "inner_iters": info["inner_iters"]}
 
 
 def serving_run(ctx, hb, torch, nreq: int) -> dict:

@@ -155,7 +155,8 @@ hub_status hub_action(hub_ctx *ctx, const hub_lattice *lat, const hub_c128 *chi,
 /* Staggered-mass Hasenbusch split (Sec. 5.1).  The pseudofermion term is replaced by
  * n+1 terms built from M_i = M(m_s = mu_i), i = 0..n-1, with M_{-1} = M(lat->ms_t)
  * (the paper's M, m_s = 0).  mt: host [n], the staggered masses as m~_i = delta*mu_i
- * (the convention of hub_lattice.ms_t), 1 <= n <= HUB_MAX_HB_MASSES.  Term i of
+ * (the convention of hub_lattice.ms_t), 0 <= n <= HUB_MAX_HB_MASSES (n = 0: the one
+ * plain pseudofermion term of eq. (hamiltonian); mt may then be NULL).  Term i of
  * pseudofermion chi_i (device [n+1][N], term order 0..n):
  *   term n   : S_n = chi_n^dag (M_{n-1} M_{n-1}^dag)^{-1} chi_n
  *   term i<n : S_i = (M_i chi_i)^dag (M_{i-1} M_{i-1}^dag)^{-1} (M_i chi_i)
@@ -163,7 +164,7 @@ hub_status hub_action(hub_ctx *ctx, const hub_lattice *lat, const hub_c128 *chi,
  * Heat-bath: chi_n = M_{n-1} rho_n and chi_i = M_i^{-1} M_{i-1} rho_i
  * = M_i^dag (M_i M_i^dag)^{-1} M_{i-1} rho_i for i < n, so that S_i = rho_i^dag rho_i.
  * rho: device [n+1][N], drawn by the caller with density e^{-rho^dag rho}.  The n
- * solves run as one batch.  info: host [n] (solve i).  opts may be NULL; use_x0 is
+ * solves run as one batch.  info: host [n] (solve i; may be NULL if n = 0).  opts may be NULL; use_x0 is
  * ignored.  Synchronises `stream`.  HUB_ERR_NOCONV if a solve missed tol (chi is
  * still written from its last iterate). */
 hub_status hub_hasenbusch_heatbath(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mt,
@@ -190,6 +191,76 @@ hub_status hub_hasenbusch_force(hub_ctx *ctx, const hub_lattice *lat, const doub
                                 int32_t n, const hub_c128 *chi, uint32_t term_mask, double scale,
                                 int32_t accumulate, double *dSdphi, double *S, hub_c128 *eta,
                                 const hub_solve_opts *opts, hub_solve_info *info, hipStream_t stream);
+
+/* Hybrid Monte Carlo update (Sec. 2) with the nested second-order Omelyan
+ * integrator of Sec. 5.2 on the Hamiltonian of eq. (hamiltonian),
+ *   H = phi^T phi / (2 U_t) + sum_{i=0..n} S_i(phi) + pi^T pi / 2,
+ * S_i the terms of the staggered-mass split above (n = 0: one plain term).
+ * Molecular dynamics: T(h) = T_F(zeta h) T_pi(h/2) T_F((1-2 zeta) h) T_pi(h/2) T_F(zeta h)
+ * with T_F(e): pi -= e dS/dphi and T_pi(e): phi += e pi.  Level k < n kicks with the
+ * force of term k and takes steps of n_scale[k] innermost steps; level n kicks with
+ * the gauge force phi/U_t plus term n and drifts phi, n_md steps of traj_length/n_md.
+ * n_scale[k+1] must divide n_scale[k] and n_scale[0] must divide n_md (the paper's
+ * N_i); an odd ratio cuts the inner step next to the middle kick in half as the
+ * paper prescribes.  zeta = 0 is the leapfrog.  The paper uses zeta = 0.193. */
+typedef struct {
+  double traj_length;                  /* trajectory length t > 0                        */
+  double zeta;                         /* Omelyan parameter in [0, 0.5]                  */
+  double U_t;                          /* delta*U > 0: variance of phi in the gauge term */
+  int32_t n_md;                        /* innermost steps per trajectory, >= 1           */
+  int32_t n;                           /* Hasenbusch masses, 0..HUB_MAX_HB_MASSES        */
+  double mt[HUB_MAX_HB_MASSES];        /* m~_i = delta*mu_i, i < n                       */
+  int32_t n_scale[HUB_MAX_HB_MASSES];  /* N_i, i < n                                     */
+  int32_t flags;                       /* 0 or HUB_HMC_CHI_GIVEN                         */
+  int32_t pad;
+} hub_hmc_params;
+
+/* hub_hmc_params.flags: the rho argument of hub_hmc_trajectory holds the
+ * pseudofermions chi_0..chi_n themselves and the heat-bath is skipped. */
+#define HUB_HMC_CHI_GIVEN 1
+
+/* One operation of the molecular-dynamics schedule: kind 0 moves phi += eps * pi;
+ * kind 1 is a group of momentum kicks at one phi, pi -= sum_l coef[l] dS_l/dphi
+ * (level l: term l, plus the gauge force for l = n).  Consecutive kicks are merged
+ * into one group (their solves run as one batch); zero kicks are dropped. */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double eps;
+  double coef[HUB_MAX_HB_MASSES + 1];
+} hub_md_op;
+
+typedef struct {
+  double dH;                                /* H(end) - H(start), FP64                  */
+  double H0, H1;                            /* the Hamiltonian at both ends             */
+  int32_t accepted;                         /* u < exp(-dH)                              */
+  int32_t kick_groups;                      /* momentum-update groups executed          */
+  int32_t drifts;                           /* phi updates executed                      */
+  int32_t reserved;
+  int64_t inner_iters;                      /* CG iterations over all solves (inner for FGMRES) */
+  int32_t force_evals[HUB_MAX_HB_MASSES + 1];  /* solves per term                        */
+  int32_t pad;
+} hub_hmc_info;
+
+/* Host only (no device call): the schedule of one trajectory.  ops: host array of
+ * max_ops entries or NULL (then only *count is set). */
+hub_status hub_md_schedule(const hub_hmc_params *params, hub_md_op *ops, int32_t max_ops, int32_t *count);
+
+/* One HMC update.  phi: device [N] float64, in/out: the accepted field (the start
+ * field again on rejection).  pi: device [N], in: the momenta drawn by the caller
+ * with density e^{-pi^2/2}; out: the momenta at the end of the trajectory (whether
+ * or not it is accepted).  rho: device [n+1][N], the heat-bath vectors (density
+ * e^{-rho^dag rho}); the pseudofermions are chi = heat-bath(rho) as in
+ * hub_hasenbusch_heatbath (with HUB_HMC_CHI_GIVEN: rho holds chi itself).
+ * u: the uniform random number of the Metropolis step,
+ * in [0, 1]; the trajectory is accepted iff u < exp(-dH).  Solves use opts (NULL =
+ * defaults); with opts->use_x0 = 1 each solve after the first of its term starts
+ * from the term's previous solution.  info: host.  Synchronises `stream`.  Returns
+ * HUB_ERR_NOCONV if a solve missed its tolerance; on any failure phi is restored
+ * to the start field and pi is left undefined. */
+hub_status hub_hmc_trajectory(hub_ctx *ctx, const hub_lattice *lat, double *phi, double *pi, const hub_c128 *rho,
+                              double u, const hub_hmc_params *params, const hub_solve_opts *opts,
+                              hub_hmc_info *info, hipStream_t stream);
 
 /* Serving: one request = solve (M M^dagger + mu2) x = chi, then S = Re chi^dagger x and
  * dS/dphi, for its own lattice, phi and shift.  Requests are admitted by workspace

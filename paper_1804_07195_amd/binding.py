@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOC
 
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
            "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
-           "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force"]
+           "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
+           "hub_md_schedule", "hub_hmc_trajectory"]
 
 
 class HubLattice(ctypes.Structure):
@@ -58,6 +59,35 @@ class HubRequest(ctypes.Structure):
 class HubKernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 16), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
+
+
+MAXM = 16  # HUB_MAX_HB_MASSES
+
+
+class HubHmcParams(ctypes.Structure):
+    _fields_ = [("traj_length", ctypes.c_double), ("zeta", ctypes.c_double), ("U_t", ctypes.c_double),
+                ("n_md", ctypes.c_int32), ("n", ctypes.c_int32), ("mt", ctypes.c_double * MAXM),
+                ("n_scale", ctypes.c_int32 * MAXM), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+HUB_HMC_CHI_GIVEN = 1
+
+
+class HubMdOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("coef", ctypes.c_double * (MAXM + 1))]
+
+
+class HubHmcInfo(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("kick_groups", ctypes.c_int32), ("drifts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("inner_iters", ctypes.c_int64),
+                ("force_evals", ctypes.c_int32 * (MAXM + 1)), ("pad", ctypes.c_int32)]
+
+    def as_dict(self, n: int) -> dict:
+        return {"dH": self.dH, "H0": self.H0, "H1": self.H1, "accepted": bool(self.accepted),
+                "kick_groups": self.kick_groups, "drifts": self.drifts, "inner_iters": self.inner_iters,
+                "force_evals": [self.force_evals[i] for i in range(n + 1)]}
 
 
 class HubError(RuntimeError):
@@ -98,6 +128,9 @@ def load() -> ctypes.CDLL:
     L.hub_hasenbusch_force.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp,
                                        ctypes.c_uint32, dbl, i32, vp, ctypes.POINTER(dbl), vp,
                                        ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
+    L.hub_md_schedule.argtypes = [ctypes.POINTER(HubHmcParams), ctypes.POINTER(HubMdOp), i32, ctypes.POINTER(i32)]
+    L.hub_hmc_trajectory.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, ctypes.POINTER(HubHmcParams),
+                                     ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubHmcInfo), vp]
     L.hub_profile_enable.argtypes = [vp, i32]
     L.hub_profile_read.argtypes = [vp, ctypes.POINTER(HubKernelStat), i32, ctypes.POINTER(i32)]
     for name in SYMBOLS:
@@ -310,6 +343,51 @@ def hub_hasenbusch_force(ctx: Context, lat: HubLattice, phi, mts, chi, terms=Non
     Sl = [S[i] if i in terms else None for i in range(n + 1)]
     il = [info[i].as_dict() if i in terms else None for i in range(n + 1)]
     return out, Sl, eta, il, st
+
+
+def hmc_params(U_t: float, n_md: int, mts=(), n_scale=(), traj_length: float = 1.0,
+               zeta: float = 0.1931833275037836, chi_given: bool = False) -> HubHmcParams:
+    """Parameters of one HMC trajectory (see hub_hmc_params in include/hub.h)."""
+    if len(mts) != len(n_scale) or len(mts) > MAXM:
+        raise ValueError("one time-scale factor per Hasenbusch mass, at most 16")
+    p = HubHmcParams()
+    p.traj_length, p.zeta, p.U_t, p.n_md, p.n = float(traj_length), float(zeta), float(U_t), int(n_md), len(mts)
+    p.flags = HUB_HMC_CHI_GIVEN if chi_given else 0
+    for i, (m, k) in enumerate(zip(mts, n_scale)):
+        p.mt[i] = float(m)
+        p.n_scale[i] = int(k)
+    return p
+
+
+def hub_md_schedule(params: HubHmcParams) -> list:
+    """The merged operation list of one trajectory: ("drift", eps) or ("kick", [coef per level])."""
+    L = load()
+    cnt = ctypes.c_int32()
+    _check(L.hub_md_schedule(ctypes.byref(params), None, 0, ctypes.byref(cnt)))
+    ops = (HubMdOp * max(cnt.value, 1))()
+    _check(L.hub_md_schedule(ctypes.byref(params), ops, cnt.value, ctypes.byref(cnt)))
+    out = []
+    for k in range(cnt.value):
+        o = ops[k]
+        out.append(("drift", o.eps) if o.kind == 0 else ("kick", [o.coef[i] for i in range(params.n + 1)]))
+    return out
+
+
+def hub_hmc_trajectory(ctx: Context, lat: HubLattice, phi, pi, rho, u: float, params: HubHmcParams,
+                       opts: HubSolveOpts | None = None, stream=None) -> dict:
+    """One HMC update in place: phi (accepted field), pi (momenta at the trajectory's end).
+    rho: device complex128 [n+1, ...] heat-bath vectors (the pseudofermions themselves if
+    the params were made with chi_given=True).  Returns the info dict."""
+    _phi(phi, lat)
+    _phi(pi, lat)
+    if _vec(rho, lat, "rho") != params.n + 1:
+        raise ValueError("rho must hold n+1 vectors")
+    o = default_opts() if opts is None else opts
+    info = HubHmcInfo()
+    _check(load().hub_hmc_trajectory(ctx.handle, ctypes.byref(lat), phi.data_ptr(), pi.data_ptr(), rho.data_ptr(),
+                                     float(u), ctypes.byref(params), ctypes.byref(o), ctypes.byref(info),
+                                     _stream(stream)))
+    return info.as_dict(params.n)
 
 
 class Pending:

@@ -13,6 +13,7 @@
 
 #include "hub.h"
 #include "hub_engine.h"
+#include "hub_md.h"
 
 using namespace hub;
 
@@ -68,6 +69,10 @@ hub_status check_opts(const hub_solve_opts& o) {
 static_assert(sizeof(hub_c128) == sizeof(double2), "hub_c128 layout");
 static_assert(HUB_MAX_BATCH == kMaxSys, "batch limit");
 static_assert(HUB_MAX_RESTART == kMaxRestart, "restart limit");
+static_assert(HUB_MAX_HB_MASSES + 1 == kMaxLevels, "Hasenbusch levels");
+static_assert(HUB_MAX_HB_MASSES + 1 <= kMaxSys, "one batched solve per term");
+static_assert(sizeof(hub_hmc_params) == 232 && sizeof(hub_md_op) == 152 && sizeof(hub_hmc_info) == 120,
+              "HMC struct layouts");
 
 // One served request.
 struct Ticket {
@@ -346,6 +351,8 @@ hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* 
   return HUB_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Solves the prepared systems (each with its own geometry, shift, right-hand side
@@ -399,6 +406,8 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const double* phi,
 }
 
 }  // namespace
+
+extern "C" {
 
 hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2, int32_t batch,
                      const hub_c128* b, hub_c128* x, const hub_solve_opts* opts, hub_solve_info* info,
@@ -486,11 +495,13 @@ hub_status hub_action(hub_ctx* ctx, const hub_lattice* lat, const hub_c128* chi,
   return HUB_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 hub_status check_masses(const double* mt, int32_t n) {
-  if (!mt) return fail(HUB_ERR_ARG, "masses is NULL");
-  if (n < 1 || n > HUB_MAX_HB_MASSES) return fail(HUB_ERR_ARG, "n must be in [1, HUB_MAX_HB_MASSES]");
+  if (n < 0 || n > HUB_MAX_HB_MASSES) return fail(HUB_ERR_ARG, "n must be in [0, HUB_MAX_HB_MASSES]");
+  if (n > 0 && !mt) return fail(HUB_ERR_ARG, "masses is NULL");
   for (int i = 0; i < n; ++i)
     if (!is_finite(mt[i])) return fail(HUB_ERR_ARG, "masses must be finite");
   return HUB_OK;
@@ -503,7 +514,109 @@ Geom geom_with_mass(const hub_lattice& lat, const double* mt, int i) {
   return make_geom(l);
 }
 
+// Heat-bath of the n+1 pseudofermions (Sec. 5.1).  Caller holds ctx->mu, device set.
+hub_status heatbath_impl(hub_ctx* ctx, const hub_lattice& lat, const double* phi, const double* mt, int n,
+                         const double2* rho, double2* chi, const hub_solve_opts& o, hub_solve_info* info,
+                         hipStream_t stream) {
+  const size_t N = (size_t)make_geom(lat).n;
+  // chi_n = M_{n-1} rho_n
+  HUB_HIP(launch_apply(geom_with_mass(lat, mt, n - 1), phi, rho + n * N, chi + n * N, 1, false, stream), "apply");
+  if (n == 0) return HUB_OK;
+  // chi_i = M_i^{-1} M_{i-1} rho_i = M_i^dag (M_i M_i^dag)^{-1} M_{i-1} rho_i, i < n
+  double2* w = (double2*)ctx->pool->alloc(2 * (size_t)n * N * 16, stream);
+  if (!w) return fail(HUB_ERR_OOM, "heat-bath workspace");
+  double2* y = w + (size_t)n * N;
+  std::vector<System> sys((size_t)n);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = launch_apply(geom_with_mass(lat, mt, i - 1), phi, rho + i * N, w + i * N, 1, false, stream);
+    sys[i].g = geom_with_mass(lat, mt, i);
+    sys[i].mu2 = 0.0;
+    sys[i].b = w + i * N;
+    sys[i].x = y + i * N;
+  }
+  hub_solve_opts oz = o;
+  oz.use_x0 = 0;
+  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, oz, stream) : hip_fail(e, "apply");
+  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+      e = launch_apply(sys[i].g, phi, y + i * N, chi + i * N, 1, true, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) result = hip_fail(e, "apply");
+    if (info)
+      for (int i = 0; i < n; ++i) info[i] = sys[i].info;
+  }
+  ctx->pool->release(w, stream);
+  return result;
+}
+
+// Actions and force of the selected terms (Sec. 5.1, eq. (f_chi_i)); term terms[k]
+// enters dSdphi with scales[k].  S and info are indexed by term.  Caller holds
+// ctx->mu, device set.  Synchronises the stream.
+hub_status eval_impl(hub_ctx* ctx, const hub_lattice& lat, const double* phi, const double* mt, int n,
+                     const double2* chi, const std::vector<int>& terms, const std::vector<double>& scales,
+                     int accumulate, double* dSdphi, double* S, double2* eta, const hub_solve_opts& o,
+                     hub_solve_info* info, hipStream_t stream) {
+  const Geom g = make_geom(lat);
+  const size_t N = (size_t)g.n;
+  const int T = (int)terms.size();
+  const int nt = ntiles_of(g.n);
+  // workspace: M_i chi_i for the ratio terms, xi per term, dot partials and results
+  const size_t vec_bytes = (size_t)T * N * 16;
+  const size_t part_bytes = (size_t)T * nt * sizeof(double);
+  char* ws = (char*)ctx->pool->alloc(2 * vec_bytes + part_bytes + 64 * sizeof(double), stream);
+  if (!ws) return fail(HUB_ERR_OOM, "Hasenbusch workspace");
+  double2* wv = (double2*)ws;
+  double2* xv = (double2*)(ws + vec_bytes);
+  double* part = (double*)(ws + 2 * vec_bytes);
+  double* res = (double*)(ws + 2 * vec_bytes + part_bytes);
+  std::vector<System> sys((size_t)T);
+  std::vector<const double2*> rhs((size_t)T);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < T && e == hipSuccess; ++k) {
+    const int i = terms[k];
+    const int den = i == n ? n - 1 : i - 1;
+    if (i == n) {
+      rhs[k] = chi + i * N;
+    } else {
+      e = launch_apply(geom_with_mass(lat, mt, i), phi, chi + i * N, wv + k * N, 1, false, stream);
+      rhs[k] = wv + k * N;
+    }
+    sys[k].g = geom_with_mass(lat, mt, den);
+    sys[k].mu2 = 0.0;
+    sys[k].b = rhs[k];
+    sys[k].x = eta + i * N;
+  }
+  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, o, stream) : hip_fail(e, "apply");
+  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
+    double Sh[kMaxSys] = {0};
+    for (int k = 0; k < T && e == hipSuccess; ++k) {
+      const int i = terms[k];
+      // S_i = Re rhs_i^dag eta_i; xi_i = M_den^dag eta_i; dS_i/dphi with xi_i (- chi_i)
+      e = launch_dot_re(g, rhs[k], eta + i * N, 1, part + (size_t)k * nt, res + k, stream);
+      if (e == hipSuccess) e = launch_apply(sys[k].g, phi, eta + i * N, xv + k * N, 1, true, stream);
+      if (e == hipSuccess && dSdphi)
+        e = launch_force(g, phi, eta + i * N, xv + k * N, scales[k], (k == 0) ? accumulate : 1, dSdphi, 1,
+                         stream, i == n ? nullptr : chi + i * N);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(Sh, res, T * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      result = hip_fail(e, "Hasenbusch force");
+    } else {
+      for (int k = 0; k < T; ++k) {
+        if (S) S[terms[k]] = Sh[k];
+        if (info) info[terms[k]] = sys[k].info;
+      }
+    }
+  }
+  ctx->pool->release(ws, stream);
+  return result;
+}
+
 }  // namespace
+
+extern "C" {
 
 hub_status hub_hasenbusch_heatbath(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mt,
                                    int32_t n, const hub_c128* rho, hub_c128* chi, const hub_solve_opts* opts,
@@ -513,7 +626,7 @@ hub_status hub_hasenbusch_heatbath(hub_ctx* ctx, const hub_lattice* lat, const d
   hub_status s = check_lattice(lat);
   if (s) return s;
   if ((s = check_masses(mt, n))) return s;
-  if (!phi || !rho || !chi || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  if (!phi || !rho || !chi || (n > 0 && !info)) return fail(HUB_ERR_ARG, "NULL buffer");
   if ((const void*)rho == (const void*)chi) return fail(HUB_ERR_ARG, "rho and chi must not overlap");
   hub_solve_opts o;
   hub_default_opts(&o);
@@ -522,34 +635,9 @@ hub_status hub_hasenbusch_heatbath(hub_ctx* ctx, const hub_lattice* lat, const d
   if ((s = check_opts(o))) return s;
   std::lock_guard<std::mutex> lk(ctx->mu);
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  const size_t N = (size_t)make_geom(*lat).n;
-  const double2* r = (const double2*)rho;
-  double2* c = (double2*)chi;
-  // chi_n = M_{n-1} rho_n
-  HUB_HIP(launch_apply(geom_with_mass(*lat, mt, n - 1), phi, r + n * N, c + n * N, 1, false, stream), "apply");
-  // chi_i = M_i^{-1} M_{i-1} rho_i = M_i^dag (M_i M_i^dag)^{-1} M_{i-1} rho_i, i < n
-  double2* w = (double2*)ctx->pool->alloc(2 * (size_t)n * N * 16, stream);
-  if (!w) return fail(HUB_ERR_OOM, "heat-bath workspace");
-  double2* y = w + (size_t)n * N;
-  std::vector<System> sys((size_t)n);
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    e = launch_apply(geom_with_mass(*lat, mt, i - 1), phi, r + i * N, w + i * N, 1, false, stream);
-    sys[i].g = geom_with_mass(*lat, mt, i);
-    sys[i].mu2 = 0.0;
-    sys[i].b = w + i * N;
-    sys[i].x = y + i * N;
-  }
-  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, o, stream) : hip_fail(e, "apply");
-  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
-    for (int i = 0; i < n && e == hipSuccess; ++i)
-      e = launch_apply(sys[i].g, phi, y + i * N, c + i * N, 1, true, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) result = hip_fail(e, "apply");
-    for (int i = 0; i < n; ++i) info[i] = sys[i].info;
-  }
-  ctx->pool->release(w, stream);
-  return result;
+  s = heatbath_impl(ctx, *lat, phi, mt, n, (const double2*)rho, (double2*)chi, o, info, stream);
+  if (s == HUB_OK && n == 0) HUB_HIP(hipStreamSynchronize(stream), "heat-bath");
+  return s;
 }
 
 hub_status hub_hasenbusch_force(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mt,
@@ -573,63 +661,196 @@ hub_status hub_hasenbusch_force(hub_ctx* ctx, const hub_lattice* lat, const doub
   if ((s = check_opts(o))) return s;
   std::lock_guard<std::mutex> lk(ctx->mu);
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  const Geom g = make_geom(*lat);
-  const size_t N = (size_t)g.n;
   std::vector<int> terms;
   for (int i = 0; i <= n; ++i)
     if (term_mask & (1u << i)) terms.push_back(i);
-  const int T = (int)terms.size();
-  const int nt = ntiles_of(g.n);
-  // workspace: M_i chi_i for the ratio terms, xi per term, dot partials and results
-  const size_t vec_bytes = (size_t)T * N * 16;
-  const size_t part_bytes = (size_t)T * nt * sizeof(double);
-  char* ws = (char*)ctx->pool->alloc(2 * vec_bytes + part_bytes + 64 * sizeof(double), stream);
-  if (!ws) return fail(HUB_ERR_OOM, "Hasenbusch workspace");
-  double2* wv = (double2*)ws;
-  double2* xv = (double2*)(ws + vec_bytes);
-  double* part = (double*)(ws + 2 * vec_bytes);
-  double* res = (double*)(ws + 2 * vec_bytes + part_bytes);
-  const double2* c = (const double2*)chi;
-  double2* et = (double2*)eta;
-  std::vector<System> sys((size_t)T);
-  std::vector<const double2*> rhs((size_t)T);
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < T && e == hipSuccess; ++k) {
-    const int i = terms[k];
-    const int den = i == n ? n - 1 : i - 1;
-    if (i == n) {
-      rhs[k] = c + i * N;
-    } else {
-      e = launch_apply(geom_with_mass(*lat, mt, i), phi, c + i * N, wv + k * N, 1, false, stream);
-      rhs[k] = wv + k * N;
+  const std::vector<double> scales(terms.size(), scale);
+  return eval_impl(ctx, *lat, phi, mt, n, (const double2*)chi, terms, scales, accumulate, dSdphi, S,
+                   (double2*)eta, o, info, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+hub_status check_hmc(const hub_hmc_params* p, MdSchedule* sched) {
+  if (!p) return fail(HUB_ERR_ARG, "params is NULL");
+  hub_status s = check_masses(p->mt, p->n);
+  if (s) return s;
+  if (!is_finite(p->U_t) || p->U_t <= 0.0) return fail(HUB_ERR_ARG, "U_t must be finite and > 0");
+  if ((p->flags & ~HUB_HMC_CHI_GIVEN) != 0) return fail(HUB_ERR_ARG, "unknown hub_hmc_params.flags");
+  if ((long long)p->n_md * (p->n + 1) > (1LL << 22)) return fail(HUB_ERR_ARG, "n_md too large");
+  std::string err;
+  if (!sched->build(p->n, p->n_scale, p->n_md, p->traj_length, p->zeta, &err)) return fail(HUB_ERR_ARG, err);
+  return HUB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hub_status hub_md_schedule(const hub_hmc_params* params, hub_md_op* ops, int32_t max_ops, int32_t* count) {
+  set_error("");
+  if (!count) return fail(HUB_ERR_ARG, "count is NULL");
+  MdSchedule sched;
+  hub_status s = check_hmc(params, &sched);
+  if (s) return s;
+  *count = (int32_t)sched.ops.size();
+  if (ops) {
+    if (max_ops < (int32_t)sched.ops.size()) return fail(HUB_ERR_ARG, "max_ops smaller than the schedule");
+    for (size_t k = 0; k < sched.ops.size(); ++k) {
+      std::memset(&ops[k], 0, sizeof(hub_md_op));
+      ops[k].kind = sched.ops[k].kind;
+      ops[k].eps = sched.ops[k].eps;
+      for (int l = 0; l <= params->n; ++l) ops[k].coef[l] = sched.ops[k].coef[l];
     }
-    sys[k].g = geom_with_mass(*lat, mt, den);
-    sys[k].mu2 = 0.0;
-    sys[k].b = rhs[k];
-    sys[k].x = et + i * N;
   }
-  hub_status result = e == hipSuccess ? run_solves(ctx, sys, phi, o, stream) : hip_fail(e, "apply");
-  if (result == HUB_OK || result == HUB_ERR_NOCONV) {
-    double Sh[64] = {0};
-    for (int k = 0; k < T && e == hipSuccess; ++k) {
-      const int i = terms[k];
-      // S_i = Re rhs_i^dag eta_i; xi_i = M_den^dag eta_i; dS_i/dphi with xi_i (- chi_i)
-      e = launch_dot_re(g, rhs[k], et + i * N, 1, part + (size_t)k * nt, res + k, stream);
-      if (e == hipSuccess) e = launch_apply(sys[k].g, phi, et + i * N, xv + k * N, 1, true, stream);
-      if (e == hipSuccess)
-        e = launch_force(g, phi, et + i * N, xv + k * N, scale, (k == 0) ? accumulate : 1, dSdphi, 1, stream,
-                         i == n ? nullptr : c + i * N);
+  return HUB_OK;
+}
+
+hub_status hub_hmc_trajectory(hub_ctx* ctx, const hub_lattice* lat, double* phi, double* pi, const hub_c128* rho,
+                              double u, const hub_hmc_params* params, const hub_solve_opts* opts,
+                              hub_hmc_info* info, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  MdSchedule sched;
+  if ((s = check_hmc(params, &sched))) return s;
+  if (!phi || !pi || !rho || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  if (!is_finite(u) || u < 0.0 || u > 1.0) return fail(HUB_ERR_ARG, "u must be in [0, 1]");
+  hub_solve_opts o;
+  hub_default_opts(&o);
+  if (opts) o = *opts;
+  if ((s = check_opts(o))) return s;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  std::memset(info, 0, sizeof(*info));
+  const int n = params->n;
+  const double* mt = params->mt;
+  const Geom g = make_geom(*lat);
+  const size_t N = (size_t)g.n;
+  const int nt2 = ntiles_of(g.n / 2);
+  // workspace: phi at the start (for a rejection), chi and eta per term, the summed
+  // pseudofermion force G, dot partials and results
+  const size_t fld = N * sizeof(double), vec = (size_t)(n + 1) * N * 16;
+  const size_t part_bytes = 2 * (size_t)nt2 * sizeof(double);
+  char* ws = (char*)ctx->pool->alloc(2 * fld + 2 * vec + part_bytes + 64 * sizeof(double), stream);
+  if (!ws) return fail(HUB_ERR_OOM, "HMC workspace");
+  double* phi0 = (double*)ws;
+  double* G = (double*)(ws + fld);
+  double2* chi = (double2*)(ws + 2 * fld);
+  double2* eta = (double2*)(ws + 2 * fld + vec);
+  double* part = (double*)(ws + 2 * fld + 2 * vec);
+  double* res = (double*)(ws + 2 * fld + 2 * vec + part_bytes);
+  hub_status result = HUB_OK;
+  auto hip_check = [&](hipError_t e, const char* where) {
+    if (e != hipSuccess && result == HUB_OK) result = hip_fail(e, where);
+    return result == HUB_OK;
+  };
+  // phi^2 / (2 U~) and pi^2 / 2 through the complex dot kernel on (re, im) pairs (N is even)
+  Geom gh = g;
+  gh.n = g.n / 2;
+  auto quadratic = [&](double* gauge, double* kin) {
+    double h[2] = {0, 0};
+    if (!hip_check(launch_dot_re(gh, (const double2*)phi, (const double2*)phi, 1, part, res, stream), "norm"))
+      return false;
+    if (!hip_check(launch_dot_re(gh, (const double2*)pi, (const double2*)pi, 1, part + nt2, res + 1, stream),
+                   "norm"))
+      return false;
+    if (!hip_check(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, stream), "norm")) return false;
+    if (!hip_check(hipStreamSynchronize(stream), "norm")) return false;
+    *gauge = 0.5 * h[0] / params->U_t;
+    *kin = 0.5 * h[1];
+    return true;
+  };
+  std::vector<double> S(n + 1, 0.0), S0(n + 1, 0.0);
+  std::vector<hub_solve_info> sinfo(n + 1);
+  std::vector<int> all(n + 1);
+  for (int i = 0; i <= n; ++i) all[i] = i;
+  bool evaluated = false;  // every term has a solution in eta (warm starts allowed)
+  auto evaluate = [&](const std::vector<int>& terms, const std::vector<double>& scales, double* dS) {
+    hub_solve_opts oe = o;
+    if (!evaluated) oe.use_x0 = 0;
+    const hub_status st = eval_impl(ctx, *lat, phi, mt, n, chi, terms, scales, 0, dS, S.data(), eta, oe,
+                                    sinfo.data(), stream);
+    if (st != HUB_OK) {
+      if (result == HUB_OK) result = st;
+      return false;
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(Sh, res, T * sizeof(double), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) {
-      result = hip_fail(e, "Hasenbusch force");
-    } else {
-      for (int k = 0; k < T; ++k) {
-        if (S) S[terms[k]] = Sh[k];
-        info[terms[k]] = sys[k].info;
+    evaluated = evaluated || terms.size() == (size_t)(n + 1);
+    for (int t : terms) {
+      info->force_evals[t]++;
+      info->inner_iters += sinfo[t].inner_iters;
+    }
+    return true;
+  };
+  double g0 = 0, k0 = 0, g1 = 0, k1 = 0;
+  bool saved = false;
+  do {
+    if (!hip_check(hipMemcpyAsync(phi0, phi, fld, hipMemcpyDeviceToDevice, stream), "copy")) break;
+    saved = true;
+    if (params->flags & HUB_HMC_CHI_GIVEN) {
+      if (!hip_check(hipMemcpyAsync(chi, rho, vec, hipMemcpyDeviceToDevice, stream), "copy")) break;
+    } else if ((result = heatbath_impl(ctx, *lat, phi, mt, n, (const double2*)rho, chi, o, nullptr, stream)) !=
+               HUB_OK) {
+      break;
+    }
+    if (!quadratic(&g0, &k0)) break;
+    // the pseudofermion actions at the start; the first kick group's forces come from the same solves
+    const MdOp& first = sched.ops.front();
+    bool first_all = first.kind == 1;
+    for (int i = 0; i <= n && first_all; ++i) first_all = first.coef[i] != 0.0;
+    if (!first_all) {
+      if (!evaluate(all, std::vector<double>(n + 1, 0.0), nullptr)) break;
+      S0 = S;
+    }
+    bool ok = true;
+    for (size_t k = 0; k < sched.ops.size() && ok; ++k) {
+      const MdOp& op = sched.ops[k];
+      if (op.kind == 0) {
+        ok = hip_check(launch_md_drift(phi, pi, op.eps, g.n, stream), "drift");
+        info->drifts++;
+        continue;
       }
+      std::vector<int> terms;
+      std::vector<double> scales;
+      for (int l = 0; l <= n; ++l)
+        if (op.coef[l] != 0.0) {
+          terms.push_back(l);
+          scales.push_back(op.coef[l]);
+        }
+      ok = evaluate(terms, scales, G);
+      if (!ok) break;
+      if (k == 0) S0 = S;
+      // pi -= sum_l coef_l dS_l/dphi - coef_n phi / U~ (the gauge force rides with level n)
+      ok = hip_check(launch_md_kick(pi, phi, G, op.coef[n] / params->U_t, g.n, stream), "kick");
+      info->kick_groups++;
     }
+    if (!ok) break;
+    // the pseudofermion actions at the end (the last kick group holds every level unless zeta = 0)
+    const MdOp& last = sched.ops.back();
+    bool last_all = last.kind == 1;
+    for (int i = 0; i <= n && last_all; ++i) last_all = last.coef[i] != 0.0;
+    if (!last_all && !evaluate(all, std::vector<double>(n + 1, 0.0), nullptr)) break;
+    if (!quadratic(&g1, &k1)) break;
+  } while (false);
+  if (result == HUB_OK) {
+    double sf0 = 0, sf1 = 0;
+    for (int i = 0; i <= n; ++i) {
+      sf0 += S0[i];
+      sf1 += S[i];
+    }
+    info->H0 = g0 + k0 + sf0;
+    info->H1 = g1 + k1 + sf1;
+    info->dH = info->H1 - info->H0;
+    info->accepted = (std::isfinite(info->dH) && u < std::exp(-info->dH)) ? 1 : 0;
+    if (!info->accepted) hip_check(hipMemcpyAsync(phi, phi0, fld, hipMemcpyDeviceToDevice, stream), "restore");
+    hip_check(hipStreamSynchronize(stream), "trajectory");
+  } else if (saved) {
+    // a failed trajectory leaves phi as it was (best effort after a device error)
+    if (hipMemcpyAsync(phi, phi0, fld, hipMemcpyDeviceToDevice, stream) == hipSuccess)
+      (void)hipStreamSynchronize(stream);
   }
   ctx->pool->release(ws, stream);
   return result;

@@ -133,6 +133,9 @@ hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, co
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
                          double* result, hipStream_t st);
 hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st);
+// phi += eps pi;  pi -= G + cg phi (G may be NULL).
+hipError_t launch_md_drift(double* phi, const double* pi, double eps, int n, hipStream_t st);
+hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double cg, int n, hipStream_t st);
 
 // Batched solver kernels over the systems of a LaunchList (descriptors in `sys`).
 // FP64 or C64 CG iteration in two stages (see hub_kernels.hip).

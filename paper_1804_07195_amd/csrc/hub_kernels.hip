@@ -558,6 +558,21 @@ __global__ __launch_bounds__(kBlock) void k_phi_to_f32(const double* __restrict_
   if (i < n) p32[i] = (float)phi[i];
 }
 
+// Molecular dynamics (Sec. 5.2): phi += eps pi (T_pi), and the momentum kick
+// pi -= G + cg phi, where G holds the summed pseudofermion force contributions
+// sum_k eps_k dS_k/dphi and cg = eps/U~ is the gauge force's share.
+__global__ __launch_bounds__(kBlock) void k_md_drift(double* __restrict__ phi, const double* __restrict__ pi,
+                                                     double eps, int n) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i < n) phi[i] += eps * pi[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, const double* __restrict__ phi,
+                                                    const double* __restrict__ G, double cg, int n) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i < n) pi[i] -= (G ? G[i] : 0.0) + cg * phi[i];
+}
+
 // ---------------------------------------------------------------------------
 // Batched solver kernels (descriptor + launch list).
 // ---------------------------------------------------------------------------
@@ -1044,6 +1059,16 @@ hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int 
   const int nt = tiles_of(g.n);
   hipLaunchKernelGGL(k_dot_re, dim3(nt * batch), dim3(kBlock), 0, st, g, a, b, nt, part);
   hipLaunchKernelGGL(k_dot_finish, dim3(batch), dim3(kBlock), 0, st, part, nt, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_drift(double* phi, const double* pi, double eps, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_md_drift, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, pi, eps, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double cg, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_md_kick, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, pi, phi, G, cg, n);
   return hipGetLastError();
 }
 

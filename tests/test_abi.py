@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_submit", "hub_poll",
               "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts",
-              "hub_profile_enable", "hub_profile_read"]:
+              "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
+              "hub_md_schedule", "hub_hmc_trajectory"]:
         assert f in names
 
 
@@ -55,6 +56,11 @@ def test_struct_layouts_match_header():
     assert b.HubSolveInfo.true_rel_resid.offset == 16
     assert b.HubRequest.opts.offset == 80
     assert ctypes.sizeof(b.HubKernelStat) == 40
+    assert ctypes.sizeof(b.HubHmcParams) == 232
+    assert b.HubHmcParams.n.offset == 28 and b.HubHmcParams.mt.offset == 32 and b.HubHmcParams.n_scale.offset == 160
+    assert ctypes.sizeof(b.HubMdOp) == 152 and b.HubMdOp.coef.offset == 16
+    assert ctypes.sizeof(b.HubHmcInfo) == 120
+    assert b.HubHmcInfo.inner_iters.offset == 40 and b.HubHmcInfo.force_evals.offset == 48
 
 
 def test_default_options(lib):
@@ -76,6 +82,12 @@ def test_argument_errors_without_a_device(lib):
         == b.HUB_ERR_ARG
     done = ctypes.c_int32()
     assert lib.hub_poll(None, ctypes.c_uint64(1), ctypes.byref(done), None) == b.HUB_ERR_ARG
+    hinfo = b.HubHmcInfo()
+    p = b.hmc_params(0.5, 4)
+    assert lib.hub_hmc_trajectory(None, ctypes.byref(lat), None, None, None, 0.5, ctypes.byref(p), None,
+                                  ctypes.byref(hinfo), None) == b.HUB_ERR_ARG
+    assert lib.hub_hasenbusch_heatbath(None, ctypes.byref(lat), None, None, 0, None, None, None, None,
+                                       None) == b.HUB_ERR_ARG
 
 
 def test_create_without_device_reports_hip_error(lib):

@@ -154,10 +154,24 @@ def test_argument_errors(hub):
                             1.0, 0, out.data_ptr(), None, eta.data_ptr(), None, info, None)
     assert L.hub_hasenbusch_force(*args(2, 0)) == hb.HUB_ERR_ARG          # no term
     assert L.hub_hasenbusch_force(*args(2, 1 << 3)) == hb.HUB_ERR_ARG     # term beyond n
-    assert L.hub_hasenbusch_force(*args(0, 1)) == hb.HUB_ERR_ARG          # n < 1
+    assert L.hub_hasenbusch_force(*args(-1, 1)) == hb.HUB_ERR_ARG         # n < 0
+    assert L.hub_hasenbusch_force(*args(0, 1 << 1)) == hb.HUB_ERR_ARG     # n = 0 has only term 0
     assert L.hub_hasenbusch_force(*args(17, 1)) == hb.HUB_ERR_ARG         # n > HUB_MAX_HB_MASSES
     assert L.hub_hasenbusch_heatbath(hub.handle, ctypes.byref(hl), pd.data_ptr(), m, 2, rd.data_ptr(),
                                      rd.data_ptr(), None, info, None) == hb.HUB_ERR_ARG  # rho == chi
     nan = (ctypes.c_double * 2)(float("nan"), 0.1)
     assert L.hub_hasenbusch_heatbath(hub.handle, ctypes.byref(hl), pd.data_ptr(), nan, 2, rd.data_ptr(),
                                      chi.data_ptr(), None, info, None) == hb.HUB_ERR_ARG
+
+
+def test_no_masses_is_the_plain_term(hub):
+    # n = 0: one pseudofermion term chi^dag (M M^dag)^{-1} chi with chi = M rho (Sec. 2)
+    hw, hl, ol, phi, rho = _setup("hb_small")
+    pd = dev(phi)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, pd, [], dev(rho[:1]))
+    assert torch.equal(chi, hb.hub_apply_M(hub, hl, pd, dev(rho[:1])))
+    F, S, eta, infos, _ = hb.hub_hasenbusch_force(hub, hl, pd, [], chi)
+    r2 = float(np.vdot(rho[0].ravel(), rho[0].ravel()).real)
+    assert abs(S[0] - r2) <= 1e-9 * r2
+    F_ref = hb.hub_force(hub, hl, pd, eta[0])
+    assert torch.equal(F, F_ref)

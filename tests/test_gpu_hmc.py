@@ -1,0 +1,150 @@
+"""GPU HMC updates (Sec. 2, 5.2) through the C ABI against the oracle's trajectory.
+
+Bars (FP64):
+* trajectory parity with the oracle (which kicks level by level and recomputes every
+  force): phi and pi at the end to 1e-9 relative (max norm), H0 and H1 to 1e-10
+  relative, dH to 1e-8 absolute, with solves at tol 1e-12;
+* reversibility: pi -> -pi retraces phi to 1e-8 (solves at 1e-12, no warm starts);
+* dH = O(dt^2): the ratio at N_MD and 2 N_MD in [3.3, 4.7];
+* rejection leaves phi bit-identical to its start;
+* at the paper's 102x102, N_t = 64 with its tuned two-mass schedule (N_MD = 30,
+  N_0 = N_1 = 2): H0 equals phi^2/(2U~) + pi^2/2 + sum |rho_i|^2 to 1e-9, and the
+  solve counts per term are those of the schedule.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hmc as ohmc
+from oracle.operator import Lattice
+from paper_1804_07195_amd import binding as hb
+from tests.gpu_helpers import dev, host
+from workloads import HASENBUSCH, HasenbuschWorkload, draw_hmc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hub():
+    ctx = hb.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _case(name, n_masses=2):
+    hw = HASENBUSCH[name]
+    if n_masses == 0:
+        hw = HasenbuschWorkload(hw.base, ())
+    w = hw.base
+    hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    ol = Lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    phi, pi, rho = draw_hmc(hw)
+    return hw, w, hl, ol, phi, pi, rho
+
+
+def _run(hub, hl, w, hw, phi, pi, rho, N, n_md, t, u=0.0, solver="cg", tol=1e-12):
+    p = hb.hmc_params(w.U_t, n_md, hw.mts, N, traj_length=t)
+    pd, qd = dev(phi), dev(pi)
+    info = hb.hub_hmc_trajectory(hub, hl, pd, qd, dev(rho), u, p, opts=hb.default_opts(solver=solver, tol=tol))
+    return host(pd), host(qd), info
+
+
+@pytest.mark.parametrize("n_masses,N,n_md,t", [(0, [], 5, 0.5), (2, [2, 1], 4, 0.5), (2, [3, 1], 6, 0.6)])
+@pytest.mark.parametrize("solver", ["cg", "fgmres"])
+def test_trajectory_matches_oracle_tiny(hub, n_masses, N, n_md, t, solver):
+    hw, w, hl, ol, phi, pi, rho = _case("hb_tiny", n_masses)
+    phi1, pi1, info = _run(hub, hl, w, hw, phi, pi, rho, N, n_md, t, solver=solver)
+    o_phi, acc, dH, H0, H1, o_pi = ohmc.hmc_update(ol, w.U_t, phi, pi, rho, hw.mts, N, n_md, u=0.0, t=t)
+    assert info["accepted"] and acc
+    scale = max(1.0, np.abs(o_phi).max())
+    assert np.abs(phi1 - o_phi).max() <= 1e-9 * scale
+    assert np.abs(pi1 - o_pi).max() <= 1e-9 * max(1.0, np.abs(o_pi).max())
+    assert abs(info["H0"] - H0) <= 1e-10 * abs(H0)
+    assert abs(info["H1"] - H1) <= 1e-10 * abs(H1)
+    assert abs(info["dH"] - dH) <= 1e-8
+
+
+def test_trajectory_matches_oracle_small(hub):
+    hw, w, hl, ol, phi, pi, rho = _case("hb_small")
+    N, n_md, t = [2, 1], 2, 0.3
+    phi1, pi1, info = _run(hub, hl, w, hw, phi, pi, rho, N, n_md, t, solver="fgmres")
+    o_phi, _, dH, H0, H1, o_pi = ohmc.hmc_update(ol, w.U_t, phi, pi, rho, hw.mts, N, n_md, u=0.0, t=t)
+    assert np.abs(phi1 - o_phi).max() <= 1e-9 * max(1.0, np.abs(o_phi).max())
+    assert np.abs(pi1 - o_pi).max() <= 1e-9 * max(1.0, np.abs(o_pi).max())
+    assert abs(info["dH"] - dH) <= 1e-8
+
+
+def test_reversibility(hub):
+    # pi -> -pi retraces phi for fixed pseudofermions (the heat-bath is drawn once)
+    hw, w, hl, ol, phi, pi, rho = _case("hb_small")
+    N, n_md, t = [2, 2], 8, 0.5
+    opts = hb.default_opts(solver="fgmres", tol=1e-12)
+    chi, _, _ = hb.hub_hasenbusch_heatbath(hub, hl, dev(phi), hw.mts, dev(rho), opts=opts)
+    p = hb.hmc_params(w.U_t, n_md, hw.mts, N, traj_length=t, chi_given=True)
+    pd, qd = dev(phi), dev(pi)
+    i1 = hb.hub_hmc_trajectory(hub, hl, pd, qd, chi, 0.0, p, opts=opts)
+    phi1 = host(pd).copy()
+    qd.neg_()
+    i2 = hb.hub_hmc_trajectory(hub, hl, pd, qd, chi, 0.0, p, opts=opts)
+    assert np.abs(phi1 - phi).max() > 1e-2
+    assert np.abs(host(pd) - phi).max() <= 1e-8
+    assert np.abs(host(qd) + pi).max() <= 1e-8
+    assert abs(i1["dH"] + i2["dH"]) <= 1e-8
+    # the given chi reproduces the heat-bath run
+    pd2, qd2 = dev(phi), dev(pi)
+    i3 = hb.hub_hmc_trajectory(hub, hl, pd2, qd2, dev(rho), 0.0, hb.hmc_params(w.U_t, n_md, hw.mts, N, traj_length=t),
+                               opts=opts)
+    assert np.abs(host(pd2) - phi1).max() <= 1e-10
+    assert abs(i3["dH"] - i1["dH"]) <= 1e-9
+
+
+def test_energy_violation_second_order(hub):
+    hw, w, hl, ol, phi, pi, rho = _case("hb_small")
+    dH = []
+    for n_md in (8, 16, 32):
+        _, _, info = _run(hub, hl, w, hw, phi, pi, rho, [2, 1], n_md, 1.0, solver="fgmres", tol=1e-11)
+        dH.append(abs(info["dH"]))
+    assert 3.3 < dH[1] / dH[2] < 4.7, dH
+
+
+def test_rejection_restores_phi(hub):
+    hw, w, hl, ol, _, _, _ = _case("hb_small")
+    for seed in range(8):
+        phi, pi, rho = draw_hmc(hw, seed=100 + seed)
+        _, _, info = _run(hub, hl, w, hw, phi, pi, rho, [2, 1], 4, 1.0)
+        if info["dH"] > 1e-9:
+            break
+    else:
+        pytest.fail("no trajectory with dH > 0 among the seeds")
+    phi1, _, info2 = _run(hub, hl, w, hw, phi, pi, rho, [2, 1], 4, 1.0, u=1.0)
+    assert not info2["accepted"] and info2["dH"] == info["dH"]
+    assert np.array_equal(phi1, phi)
+
+
+def test_argument_errors(hub):
+    hw, w, hl, ol, phi, pi, rho = _case("hb_tiny")
+    pd, qd, rd = dev(phi), dev(pi), dev(rho)
+    for bad in (dict(N=[3, 1], n_md=4), dict(N=[2, 4], n_md=8), dict(N=[2, 1], n_md=0)):
+        p = hb.hmc_params(w.U_t, bad["n_md"], hw.mts, bad["N"])
+        with pytest.raises(hb.HubError):
+            hb.hub_hmc_trajectory(hub, hl, pd, qd, rd, 0.0, p)
+    p = hb.hmc_params(w.U_t, 4, hw.mts, [2, 1])
+    with pytest.raises(hb.HubError):
+        hb.hub_hmc_trajectory(hub, hl, pd, qd, rd, 1.5, p)  # u outside [0, 1]
+    p0 = hb.hmc_params(-1.0, 4, hw.mts, [2, 1])
+    with pytest.raises(hb.HubError):
+        hb.hub_hmc_trajectory(hub, hl, pd, qd, rd, 0.0, p0)  # U_t <= 0
+
+
+def test_full_size_paper_schedule(hub):
+    hw, w, hl, ol, phi, pi, rho = _case("hb_large")
+    p = hb.hmc_params(w.U_t, 30, hw.mts, [2, 2], traj_length=1.0)
+    pd, qd = dev(phi), dev(pi)
+    info = hb.hub_hmc_trajectory(hub, hl, pd, qd, dev(rho), 0.0, p, opts=hb.default_opts(solver="fgmres"))
+    r2 = sum(float(np.vdot(r.ravel(), r.ravel()).real) for r in rho)
+    H0 = 0.5 * float(np.sum(phi * phi)) / w.U_t + 0.5 * float(np.sum(pi * pi)) + r2
+    assert abs(info["H0"] - H0) <= 1e-9 * H0
+    assert info["force_evals"] == [31, 31, 61]
+    assert np.isfinite(info["dH"]) and abs(info["dH"]) < 50
+    assert info["accepted"]
+    assert float(torch.linalg.norm(pd - dev(phi))) > 1.0

@@ -22,7 +22,7 @@ import math
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "HasenbuschWorkload", "HASENBUSCH", "draw_phi", "draw_gaussian_c128",
-           "draw_inputs", "draw_hasenbusch"]
+           "draw_inputs", "draw_hasenbusch", "draw_hmc"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -146,6 +146,17 @@ def draw_hasenbusch(hw: HasenbuschWorkload, seed: int | None = None):
     """Return (phi, rho) for a Hasenbusch workload: rho [n+1, N_t, 2, L1, L2] holds the
     heat-bath vectors rho_0 .. rho_n (drawn phi first, then rho_0, rho_1, ...)."""
     return draw_inputs(hw.base, seed=seed, batch=hw.nterms)
+
+
+def draw_hmc(hw: HasenbuschWorkload, seed: int | None = None):
+    """Return (phi, pi, rho) for one HMC update: phi as in draw_phi, momenta pi ~ N(0, 1)
+    (weight exp(-pi^2/2)) float64 [N_t, 2, L1, L2], then rho_0 .. rho_n (drawn in that order)."""
+    w = hw.base
+    rng = np.random.default_rng(w.seed if seed is None else seed)
+    phi = draw_phi(rng, w)
+    pi = rng.standard_normal(size=w.shape)
+    rho = np.stack([draw_gaussian_c128(rng, w.shape) for _ in range(hw.nterms)])
+    return phi, pi, rho
 
 
 def serving_stream(n: int, seed: int = 5, rate: float = 200.0,
