@@ -26,20 +26,26 @@ complex128 / float64 with NumPy and SciPy sparse matrices:
                 integrator of Sec. 5.2 and the Metropolis step;
 * `multishift` - several shifts mu^2 of one right-hand side (plain solves and the
                 shared-Krylov CG-M), Lanczos extremes of M M^dagger from the CG
-                coefficients, and the Hasenbusch masses of eq. (mu_i_eqn).
+                coefficients, and the Hasenbusch masses of eq. (mu_i_eqn);
+* `ed`        - exact diagonalisation of the Hubbard Hamiltonian on the 4-site
+                (2 x 1 cells) honeycomb of Sec. 7.2: quasi-particle energies and
+                thermal correlators;
+* `correlators` - single-particle correlators from M^{-1} and the exponential fits
+                that extract quasi-particle energies (Sec. 7.2).
 
 Every function is pinned by a test in `tests/test_oracle_pins.py` or
 `tests/test_oracle_hasenbusch.py`, `tests/test_oracle_hmc.py` or
-`tests/test_oracle_multishift.py` against a
+`tests/test_oracle_multishift.py`, `tests/test_oracle_ed.py`,
+`tests/test_oracle_correlators.py` against a
 closed form, an invariance or brute force that does not reuse its code.
 """
 from .operator import Lattice, build_M, build_M_dense_loops, apply_M, apply_Mdag, normal_apply, site_index
 from .solve import solve, solve_dense, cg, true_rel_residual, fgmres_alg_a1
 from .force import action, force, xi_from_eta
-from . import hasenbusch, hmc, multishift
+from . import correlators, ed, hasenbusch, hmc, multishift
 
 __all__ = [
     "Lattice", "build_M", "build_M_dense_loops", "apply_M", "apply_Mdag", "normal_apply", "site_index",
     "solve", "solve_dense", "cg", "true_rel_residual", "fgmres_alg_a1",
-    "action", "force", "xi_from_eta", "hasenbusch", "hmc", "multishift",
+    "action", "force", "xi_from_eta", "hasenbusch", "hmc", "multishift", "ed", "correlators",
 ]
