@@ -13,10 +13,12 @@ bandwidth, the FP64 CG comparison, a short serving run and the CPU oracle baseli
 
 Further legs (not part of the step): the staggered-mass Hasenbusch split at the
 same lattice with the paper's tuned two masses (heat-bath, all-terms and per-term
-force evaluations), and one full HMC trajectory with the paper's nested Omelyan
-schedule for that lattice.
+force evaluations), one full HMC trajectory with the paper's nested Omelyan
+schedule for that lattice, and the shared-Krylov multi-shift CG with its Lanczos
+spectral bounds against batched separate solves.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-hasenbusch] [--no-hmc]
+       [--no-multishift]
 """
 from __future__ import annotations
 
@@ -53,6 +55,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-hasenbusch", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
+    ap.add_argument("--no-multishift", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     return ap.parse_args()
@@ -262,6 +265,8 @@ def main():
         out["hasenbusch"] = hasenbusch_run(ctx, hb, torch)
     if not args.no_hmc:
         out["hmc"] = hmc_run(ctx, hb, torch)
+    if not args.no_multishift:
+        out["multishift"] = multishift_run(ctx, hb, torch)
     if not args.no_serving:
         out["serving"] = serving_run(ctx, hb, torch, args.serving_requests)
     ctx.close()
@@ -361,6 +366,47 @@ def hmc_run(ctx, hb, torch) -> dict:
             "seconds_per_trajectory": round(sec, 3), "dH": info["dH"], "accepted_at_u_0.5": info["accepted"],
             "force_evals_per_term": info["force_evals"], "kick_groups": info["kick_groups"],
             "drifts": info["drifts"], "inner_iters": info["inner_iters"]}
+
+
+def multishift_run(ctx, hb, torch, reps: int = 3) -> dict:
+    """One right-hand side, several shifts: the shared-Krylov FP64 multi-shift CG against
+    the same shifts solved as a batch of separate FP64 CG and mixed FGMRES systems, at
+    48x48x64 (mu2 in {0.5, 0.05, 0}) and 102x102x64 (mu2 in {0.1, 0}); the Lanczos
+    bounds of M M^dagger and the two Hasenbusch masses they give by eq. (mu_i_eqn)."""
+    res = {}
+    for name, shifts in (("medium3", [0.5, 0.05, 0.0]), ("large2", [0.1, 0.0])):
+        w = WORKLOADS[name]
+        hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+        phi, eta = draw_inputs(w, batch=1)
+        pd = torch.from_numpy(phi).to("cuda")
+        b = torch.from_numpy(eta[0]).to("cuda")
+        bb = b[None].expand(len(shifts), *b.shape).contiguous()
+        x = torch.empty_like(bb)
+        row = {"shifts": shifts}
+
+        def t_of(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = fn()
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0) / reps, out
+
+        ms_ms, (_, infos, lam, _) = t_of(lambda: hb.hub_solve_multishift(ctx, hl, pd, shifts, b, x=x))
+        cg_ms, (_, icg, _) = t_of(lambda: hb.hub_solve(ctx, hl, pd, shifts, bb, x=x,
+                                                        opts=hb.default_opts(solver="cg")))
+        fg_ms, (_, ifg, _) = t_of(lambda: hb.hub_solve(ctx, hl, pd, shifts, bb, x=x,
+                                                        opts=hb.default_opts(solver="fgmres")))
+        row.update({"multishift_ms": round(ms_ms, 3), "shared_iters": infos[0]["outer_iters"],
+                    "certify_iters": [i["inner_iters"] for i in infos],
+                    "true_rel_resid": [i["true_rel_resid"] for i in infos],
+                    "batched_fp64_cg_ms": round(cg_ms, 3), "batched_fp64_cg_iters": [i["inner_iters"] for i in icg],
+                    "batched_fgmres_ms": round(fg_ms, 3),
+                    "lanczos_lambda_min": lam[0], "lanczos_lambda_max": lam[1],
+                    "hasenbusch_masses_eq_mu_i_n2": hb.hub_hasenbusch_masses(lam[0], lam[1], 2)})
+        res[f"{w.L1}x{w.L2}x{w.Nt}"] = row
+    return res
 
 
 def serving_run(ctx, hb, torch, nreq: int) -> dict:

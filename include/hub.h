@@ -41,6 +41,7 @@ extern "C" {
 #define HUB_MAX_BATCH 64     /* systems per hub_apply_* / hub_solve / hub_force call */
 #define HUB_MAX_RESTART 20   /* largest FGMRES restart length m                      */
 #define HUB_MAX_HB_MASSES 16 /* staggered Hasenbusch masses per hub_hasenbusch_* call */
+#define HUB_MAX_SHIFTS 17    /* shifts per hub_solve_multishift call                 */
 
 typedef struct { double re, im; } hub_c128;
 
@@ -151,6 +152,28 @@ hub_status hub_force(hub_ctx *ctx, const hub_lattice *lat, const double *phi, co
  * chi, eta: device [batch][N]; S: host float64 [batch].  Synchronises `stream`. */
 hub_status hub_action(hub_ctx *ctx, const hub_lattice *lat, const hub_c128 *chi, const hub_c128 *eta,
                       int32_t batch, double *S, hipStream_t stream);
+
+/* Several shifts of one right-hand side: x_s = (M M^dagger + mu2[s])^{-1} b for
+ * s < nshift, from one shared Krylov space (Sec. 5.1 shifts; the paper names
+ * multi-shift solvers without giving one: this is CG for shifted systems).  One FP64
+ * CG runs on the smallest shift; the other systems follow through scalar
+ * recurrences and stop updating once their own residual meets tol.  Every x_s is
+ * then certified by its FP64 true residual (a warm-started CG that returns at once
+ * when the tolerance is met, else finishes the solve).  b: device [N]; x: device
+ * [nshift][N]; mu2: host [nshift]; info: host [nshift] (outer_iters = shared Krylov
+ * iterations, inner_iters = iterations of the certifying CG).  opts: tol, max_iter,
+ * check_every (solver and use_x0 are ignored).  lambda: host [2] or NULL; receives
+ * the extreme eigenvalues of the Lanczos matrix of the shared CG (its coefficients
+ * alpha_k, beta_k), shifted back to M M^dagger: estimates of lambda_min and
+ * lambda_max of eq. (solver_time_eqn).  Synchronises `stream`. */
+hub_status hub_solve_multishift(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mu2,
+                                int32_t nshift, const hub_c128 *b, hub_c128 *x, const hub_solve_opts *opts,
+                                hub_solve_info *info, double *lambda, hipStream_t stream);
+
+/* Host only: n Hasenbusch masses spaced geometrically between the spectral bounds,
+ * mu_i = lambda_min (lambda_max / lambda_min)^((i+1)/(n+1)), i < n (eq. (mu_i_eqn)).
+ * mu: host [n]; needs 0 < lambda_min < lambda_max and 1 <= n <= HUB_MAX_HB_MASSES. */
+hub_status hub_hasenbusch_masses(double lambda_min, double lambda_max, int32_t n, double *mu);
 
 /* Staggered-mass Hasenbusch split (Sec. 5.1).  The pseudofermion term is replaced by
  * n+1 terms built from M_i = M(m_s = mu_i), i = 0..n-1, with M_{-1} = M(lat->ms_t)

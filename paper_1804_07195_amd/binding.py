@@ -22,13 +22,14 @@ HUB_CG_FP64, HUB_FGMRES_MIXED = 0, 1
 HUB_MAX_BATCH = 64
 HUB_MAX_RESTART = 20
 HUB_MAX_HB_MASSES = 16
+HUB_MAX_SHIFTS = 17
 STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOCONV", 4: "HUB_ERR_HIP",
                 5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
 
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
            "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
            "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
-           "hub_md_schedule", "hub_hmc_trajectory"]
+           "hub_md_schedule", "hub_hmc_trajectory", "hub_solve_multishift", "hub_hasenbusch_masses"]
 
 
 class HubLattice(ctypes.Structure):
@@ -131,6 +132,10 @@ def load() -> ctypes.CDLL:
     L.hub_md_schedule.argtypes = [ctypes.POINTER(HubHmcParams), ctypes.POINTER(HubMdOp), i32, ctypes.POINTER(i32)]
     L.hub_hmc_trajectory.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, ctypes.POINTER(HubHmcParams),
                                      ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubHmcInfo), vp]
+    L.hub_solve_multishift.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
+                                       ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo),
+                                       ctypes.POINTER(dbl), vp]
+    L.hub_hasenbusch_masses.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
     L.hub_profile_enable.argtypes = [vp, i32]
     L.hub_profile_read.argtypes = [vp, ctypes.POINTER(HubKernelStat), i32, ctypes.POINTER(i32)]
     for name in SYMBOLS:
@@ -343,6 +348,36 @@ def hub_hasenbusch_force(ctx: Context, lat: HubLattice, phi, mts, chi, terms=Non
     Sl = [S[i] if i in terms else None for i in range(n + 1)]
     il = [info[i].as_dict() if i in terms else None for i in range(n + 1)]
     return out, Sl, eta, il, st
+
+
+def hub_solve_multishift(ctx: Context, lat: HubLattice, phi, mu2, b, x=None, opts: HubSolveOpts | None = None,
+                         stream=None, allow_noconv: bool = False):
+    """x_s = (M M^dagger + mu2[s])^{-1} b for every shift from one Krylov space.
+    b: device complex128 with N entries.  Returns (x [nshift, ...], [info dicts],
+    (lambda_min, lambda_max) of M M^dagger from the Lanczos coefficients, status)."""
+    _phi(phi, lat)
+    if _vec(b, lat, "b") != 1:
+        raise ValueError("one right-hand side")
+    ns = len(mu2)
+    if x is None:
+        x = torch.empty((ns,) + tuple(b.shape[-4:]), dtype=torch.complex128, device=b.device)
+    if _vec(x, lat, "x") != ns:
+        raise ValueError("x must hold one vector per shift")
+    mu = (ctypes.c_double * ns)(*[float(m) for m in mu2])
+    lam = (ctypes.c_double * 2)()
+    o = default_opts() if opts is None else opts
+    info = (HubSolveInfo * ns)()
+    st = load().hub_solve_multishift(ctx.handle, ctypes.byref(lat), phi.data_ptr(), mu, ns, b.data_ptr(),
+                                     x.data_ptr(), ctypes.byref(o), info, lam, _stream(stream))
+    _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
+    return x, [i.as_dict() for i in info], (lam[0], lam[1]), st
+
+
+def hub_hasenbusch_masses(lambda_min: float, lambda_max: float, n: int) -> list:
+    """eq. (mu_i_eqn): n masses geometric between the spectral bounds (host only)."""
+    mu = (ctypes.c_double * n)()
+    _check(load().hub_hasenbusch_masses(float(lambda_min), float(lambda_max), int(n), mu))
+    return list(mu)
 
 
 def hmc_params(U_t: float, n_md: int, mts=(), n_scale=(), traj_length: float = 1.0,

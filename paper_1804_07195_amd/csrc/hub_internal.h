@@ -83,6 +83,43 @@ struct SysDesc {
   void* vec[kMaxSlots];  // vector slots (type fixed by the slot's role)
 };
 
+// Multi-shift CG (FP64): one CG on A_0 = M M^dag + mu2 carrying the shifted systems
+// (A_0 + sigma_s) x_s = b through the scalar recurrences of the shared Krylov space.
+constexpr int kMsMax = 16;  // shifted systems per solve
+struct MsScal {
+  double rrv[2];              // |r_k|^2 in rrv[k & 1]
+  double alpha[2];            // alpha_k in alpha[k & 1]; alpha[1] = 1 stands for alpha_{-1}
+  double beta[2];             // beta_k in beta[k & 1]; beta[1] = 0 stands for beta_{-1}
+  double stop2;               // tol^2 |b|^2 (base and shifted residuals)
+  double pad0;
+  double zeta[kMsMax][3];     // zeta^s_k in zeta[s][k % 3]
+  int frozen[kMsMax][2];      // shift s done updating after step k: frozen[s][(k+1) & 1]
+  int iters, maxit, active;
+  int stop;                   // set by the stage 1 that stops; the next stage 2 clears active
+};
+struct MsDesc {
+  Geom g;
+  const double* phi;
+  double mu2;                 // shift of the base system
+  const double2* b;
+  double2* x;                 // base solution
+  double2* r;
+  double2* p[2];
+  double2* u;
+  double2* xs[kMsMax];        // shifted solutions
+  double2* ps[kMsMax];        // shifted search directions
+  double sigma[kMsMax];       // mu2_s - mu2 >= 0
+  int ns;
+  int ntiles;
+  double* part1;
+  double* part2;
+  MsScal* sc;
+  double* hist;               // alpha_k at [2k], beta_k at [2k+1] (Lanczos coefficients)
+  double tol2;
+  int maxit;
+  int pad;
+};
+
 // Systems of one batched launch: workgroup tiles are laid out system after system.
 struct LaunchList {
   int nsys;
@@ -144,6 +181,11 @@ hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, 
 // kernel's own start and end timestamps into them (hipExtLaunchKernel).
 hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Multi-shift CG: start (r = b, x = 0, x_s = 0, p_s = b, partial |b|^2), setup (one
+// workgroup: scalars), and the two stages of iteration `it` (shifted updates of step
+// it-1 ride in stage 1, where beta_{it-1} is known).
+hipError_t launch_ms_start(const MsDesc* d, int ntiles, hipStream_t st);
+hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st);
 // Algorithmic bytes per site of each CG stage (reads + writes of distinct vectors).
 constexpr double kCgBytes[2][2] = {{72.0, 104.0}, {36.0, 52.0}};  // [single][stage-1]
 // u = M^dagger in; in is an FP64 slot or (in_c64) a C64 slot; u is S_U.

@@ -765,6 +765,217 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
   if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-shift CG (FP64).  Base CG on A_0 as k_cg1 / k_cg2; every shifted system s
+// follows with x_s += alpha^s_k p^s_k, p^s_{k+1} = zeta^s_{k+1} r_{k+1} + beta^s_k p^s_k,
+//   zeta^s_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
+//                  (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 + sigma_s alpha_k)),
+//   alpha^s_k = alpha_k zeta_{k+1} / zeta_k,  beta^s_k = beta_k (zeta_{k+1} / zeta_k)^2,
+// until its residual |zeta^s| |r| meets the tolerance.  Every workgroup evaluates the
+// scalar recurrences in the same order (one thread per shift), so they agree.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_ms_start(const MsDesc* __restrict__ d) {
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int base = tile * kTile + threadIdx.x;
+  const int n_sites = d->g.n;
+  double acc = 0.0;
+  const double2 z = {0.0, 0.0};
+  for (int m = 0; m < kSitesPerThread; ++m) {
+    const int n = base + m * kBlock;
+    if (n >= n_sites) break;
+    const double2 v = d->b[n];
+    d->r[n] = v;
+    d->x[n] = z;
+    for (int s = 0; s < d->ns; ++s) {
+      d->xs[s][n] = z;
+      d->ps[s][n] = v;
+    }
+    acc += v.x * v.x + v.y * v.y;
+  }
+  const double tot = block_sum(acc);
+  if (threadIdx.x == 0) d->part2[tile] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ms_setup(const MsDesc* __restrict__ d) {
+  const double rr = sum_partials(d->part2, d->ntiles, 1);
+  if (threadIdx.x == 0) {
+    MsScal* sc = d->sc;
+    sc->rrv[0] = rr;
+    sc->rrv[1] = rr;
+    sc->alpha[0] = 1.0;
+    sc->alpha[1] = 1.0;
+    sc->beta[0] = 0.0;
+    sc->beta[1] = 0.0;
+    sc->stop2 = d->tol2 * rr;
+    for (int s = 0; s < kMsMax; ++s) {
+      sc->zeta[s][0] = sc->zeta[s][1] = sc->zeta[s][2] = 1.0;
+      sc->frozen[s][0] = sc->frozen[s][1] = 0;
+    }
+    sc->iters = 0;
+    sc->maxit = d->maxit;
+    sc->stop = 0;
+    __hip_atomic_store(&sc->active, rr > 0.0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ int ms_load_active(MsScal* sc) {
+  return __hip_atomic_load(&sc->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Stage 1 of iteration it: |r_it|^2, beta_{it-1}, the shifted scalars of step it-1 and
+// the stopping test; p_it = r_it + beta p_{it-1}, u = M^dagger p_it, partial <p, A_0 p>;
+// then the shifted vector updates of step it-1 (also in the iteration that stops).
+__global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, int it) {
+  MsScal* sc = d->sc;
+  if (!ms_load_active(sc)) return;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const Geom g = d->g;
+  const int base = tile * kTile + threadIdx.x;
+  const double mu2 = d->mu2;
+  const int ns = d->ns;
+  const Vec<double2> r(d->r), po(d->p[it & 1]), pn(d->p[1 - (it & 1)]), u(d->u);
+  const Real<double> phi(d->phi);
+  __shared__ double s_as[kMsMax], s_bs[kMsMax], s_zn[kMsMax];
+  __shared__ int s_live[kMsMax];
+  double beta = 0.0;
+  bool stopped = false;
+  auto mid = [&]() -> bool {
+    const double rr = sum_partials(d->part2, d->ntiles, 1);
+    const double rr_prev = sc->rrv[(it - 1) & 1];
+    beta = rr / rr_prev;
+    const int k = it - 1;
+    const double a_k = sc->alpha[k & 1], a_km = sc->alpha[(k + 1) & 1], b_km = sc->beta[(k + 1) & 1];
+    if ((int)threadIdx.x < ns) {
+      const int s = threadIdx.x;
+      const bool live = sc->frozen[s][k & 1] == 0;
+      const double zk = sc->zeta[s][k % 3], zkm = sc->zeta[s][(k + 2) % 3];
+      double zn = zk, as = 0.0, bs = 1.0;
+      if (live) {
+        zn = zk * zkm * a_km / (a_k * b_km * (zkm - zk) + zkm * a_km * (1.0 + d->sigma[s] * a_k));
+        as = a_k * zn / zk;
+        bs = beta * (zn / zk) * (zn / zk);
+      }
+      s_as[s] = as;
+      s_bs[s] = bs;
+      s_zn[s] = zn;
+      s_live[s] = live ? 1 : 0;
+      if (tile == 0) {
+        sc->zeta[s][(k + 1) % 3] = zn;
+        sc->frozen[s][(k + 1) & 1] = (!live || zn * zn * rr <= sc->stop2) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const bool first = (tile == 0 && threadIdx.x == 0);
+    if (first) {
+      sc->rrv[it & 1] = rr;
+      sc->beta[k & 1] = beta;
+      d->hist[2 * k + 1] = beta;
+    }
+    if (!(rr > sc->stop2) || it >= sc->maxit) {
+      // every workgroup of this launch still runs (active stays set until the next
+      // stage 2), so all of them apply the last shifted updates below
+      if (first) {
+        sc->iters = it;
+        sc->stop = 1;
+      }
+      stopped = true;
+      return false;
+    }
+    return true;
+  };
+  double acc = 0.0;
+  auto pre = [](int) { return NoPre{}; };
+  auto post = [&](int n, double2 uu, double2 p, NoPre) {
+    pn.set(n, p);
+    u.set(n, uu);
+    acc += norm2<double>(uu) + mu2 * norm2<double>(p);
+  };
+  if (it == 0) {
+    auto ld = [=](int k) { return r[k]; };
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+  } else {
+    auto ld = [=](int k) { return RP<double2>{r[k], po[k]}; };
+    auto cook = [&](RP<double2> v) {
+      double2 o;
+      o.x = v.r.x + beta * v.p.x;
+      o.y = v.r.y + beta * v.p.y;
+      return o;
+    };
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, ld, cook, pre, mid, post);
+    // shifted systems, step it-1 -> it
+    for (int m = 0; m < kSitesPerThread; ++m) {
+      const int n = base + m * kBlock;
+      if (n >= g.n) break;
+      const double2 rv = r[n];
+      for (int s = 0; s < ns; ++s) {
+        if (!s_live[s]) continue;
+        const Vec<double2> xs(d->xs[s]), ps(d->ps[s]);
+        const double2 pv = ps[n];
+        double2 xv = xs[n];
+        xv.x += s_as[s] * pv.x;
+        xv.y += s_as[s] * pv.y;
+        double2 q;
+        q.x = s_zn[s] * rv.x + s_bs[s] * pv.x;
+        q.y = s_zn[s] * rv.y + s_bs[s] * pv.y;
+        xs.set(n, xv);
+        ps.set(n, q);
+      }
+    }
+  }
+  if (stopped) return;
+  const double tot = block_sum(acc);
+  if (threadIdx.x == 0) Real<double>(d->part1).set(tile, tot);
+}
+
+// Stage 2 of iteration it: alpha_it = |r_it|^2 / <p, A_0 p>, q = M u + mu2 p,
+// x += alpha p, r -= alpha q, partial |r_{it+1}|^2.
+__global__ __launch_bounds__(kBlock) void k_ms2(const MsDesc* __restrict__ d, int it) {
+  MsScal* sc = d->sc;
+  if (!ms_load_active(sc)) return;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  if (sc->stop) {
+    if (tile == 0 && threadIdx.x == 0)
+      __hip_atomic_store(&sc->active, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  const Geom g = d->g;
+  const int base = tile * kTile + threadIdx.x;
+  const double mu2 = d->mu2;
+  double alpha = 0.0;
+  auto mid = [&]() -> bool {
+    const double pq = sum_partials(d->part1, d->ntiles, 1);
+    alpha = sc->rrv[it & 1] / pq;
+    if (tile == 0 && threadIdx.x == 0) {
+      sc->alpha[it & 1] = alpha;
+      d->hist[2 * it] = alpha;
+    }
+    return true;
+  };
+  const Vec<double2> p(d->p[1 - (it & 1)]), u(d->u), x(d->x), r(d->r);
+  const Real<double> phi(d->phi);
+  struct Own {
+    double2 p, x, r;
+  };
+  double acc = 0.0;
+  auto ld = [=](int k) { return u[k]; };
+  auto pre = [=](int n) { return Own{p[n], x[n], r[n]}; };
+  auto post = [&](int n, double2 q, double2, Own o) {
+    q.x += mu2 * o.p.x;
+    q.y += mu2 * o.p.y;
+    double2 xv = o.x, rv = o.r;
+    xv.x += alpha * o.p.x;
+    xv.y += alpha * o.p.y;
+    rv.x -= alpha * q.x;
+    rv.y -= alpha * q.y;
+    x.set(n, xv);
+    r.set(n, rv);
+    acc += norm2<double>(rv);
+  };
+  stencil_sites<double, false, HUB_SPT64>(g, phi, base, ld, Same{}, pre, mid, post);
+  const double tot = block_sum(acc);
+  if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
+}
+
 template <typename Tin> __device__ __forceinline__ double2 to_c128(Tin v);
 template <> __device__ __forceinline__ double2 to_c128<double2>(double2 v) { return v; }
 template <> __device__ __forceinline__ double2 to_c128<float2>(float2 v) {
@@ -1069,6 +1280,18 @@ hipError_t launch_md_drift(double* phi, const double* pi, double eps, int n, hip
 
 hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double cg, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_md_kick, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, pi, phi, G, cg, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_start(const MsDesc* d, int ntiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_ms_start, dim3(ntiles), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_ms_setup, dim3(1), dim3(kBlock), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st) {
+  hipLaunchKernelGGL(k_ms1, dim3(ntiles), dim3(kBlock), 0, st, d, it);
+  hipLaunchKernelGGL(k_ms2, dim3(ntiles), dim3(kBlock), 0, st, d, it);
   return hipGetLastError();
 }
 

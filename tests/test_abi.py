@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
     for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_submit", "hub_poll",
               "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts",
               "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
-              "hub_md_schedule", "hub_hmc_trajectory"]:
+              "hub_md_schedule", "hub_hmc_trajectory", "hub_solve_multishift", "hub_hasenbusch_masses"]:
         assert f in names
 
 
@@ -88,6 +88,19 @@ def test_argument_errors_without_a_device(lib):
                                   ctypes.byref(hinfo), None) == b.HUB_ERR_ARG
     assert lib.hub_hasenbusch_heatbath(None, ctypes.byref(lat), None, None, 0, None, None, None, None,
                                        None) == b.HUB_ERR_ARG
+
+
+def test_hasenbusch_masses_host_helper(lib):
+    from oracle.multishift import hasenbusch_masses
+    from paper_1804_07195_amd import binding as b
+    for n in (1, 2, 5):
+        got = b.hub_hasenbusch_masses(0.054, 4.1, n)
+        want = hasenbusch_masses(0.054, 4.1, n)
+        assert all(abs(g - w) <= 1e-15 * w for g, w in zip(got, want))
+    out = (ctypes.c_double * 2)()
+    assert lib.hub_hasenbusch_masses(0.5, 0.1, 2, out) == b.HUB_ERR_ARG
+    assert lib.hub_hasenbusch_masses(0.1, 0.5, 0, out) == b.HUB_ERR_ARG
+    assert lib.hub_solve_multishift(None, None, None, None, 1, None, None, None, None, None, None) == b.HUB_ERR_ARG
 
 
 def test_create_without_device_reports_hip_error(lib):

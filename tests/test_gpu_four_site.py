@@ -1,0 +1,57 @@
+"""The 4-site benchmark (Sec. 7.2) on the GPU: correlator measurement and a short ensemble.
+
+* the correlators measured with the library's solves on a given field equal the
+  oracle's correlators of the same field (dense M^{-1}) to 1e-8;
+* free field: the fitted energies are the free 3 kappa and kappa up to the O(delta^2)
+  discretisation (below 5e-3 at N_t = 128);
+* a short multi-chain ensemble at U/kappa = 4, beta kappa = 8 runs with finite energies
+  and a sensible acceptance (the physics comparison with exact diagonalisation needs
+  long runs and is made by the benchmark).
+"""
+import numpy as np
+import pytest
+
+from oracle import correlators as oc
+from oracle.operator import Lattice
+from paper_1804_07195_amd import binding as hb
+from paper_1804_07195_amd import four_site
+from tests.gpu_helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hub():
+    ctx = hb.Context(0)
+    yield ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("Nt", [16, 64])
+def test_measurement_matches_oracle(hub, Nt):
+    d = 8.0 / Nt
+    hl, ol = hb.lattice(2, 1, Nt, d), Lattice(2, 1, Nt, d)
+    rng = np.random.default_rng(Nt)
+    phi = rng.normal(0, np.sqrt(4 * d), ol.shape)
+    t0s = [0, Nt // 4, Nt // 2, 3 * Nt // 4]
+    got = four_site.measure(hub, hl, dev(phi), t0s, opts=hb.default_opts(tol=1e-13))
+    for name, v in (("Gamma", oc.GAMMA), ("M", oc.M_POINT)):
+        want = oc.propagator_correlator(ol, phi, v, t0s=t0s)
+        assert np.max(np.abs(got[name] - want)) <= 1e-8 * np.max(np.abs(want)), name
+
+
+def test_free_field_energies(hub):
+    Nt = 128
+    d = 8.0 / Nt
+    hl = hb.lattice(2, 1, Nt, d)
+    m = four_site.measure(hub, hl, dev(np.zeros((Nt, 2, 2, 1))), [0, 64])
+    assert abs(four_site.fit_energy(m["Gamma"], d, four_site.WINDOWS["Gamma"]) - 3.0) < 5e-3
+    assert abs(four_site.fit_energy(m["M"], d, four_site.WINDOWS["M"]) - 1.0) < 5e-3
+
+
+def test_short_ensemble_runs():
+    r = four_site.run(32, n_chains=4, n_therm=5, n_meas=20, n_md=6, bin_size=5, n_boot=50)
+    assert r["measured"] == 80
+    assert 0.3 < r["acceptance"] <= 1.0
+    assert np.isfinite(r["E_Gamma"]) and np.isfinite(r["E_M"])
+    assert 2.0 < r["E_Gamma"] < 5.0 and 0.5 < r["E_M"] < 3.0
