@@ -285,6 +285,17 @@ hub_status hub_hmc_trajectory(hub_ctx *ctx, const hub_lattice *lat, double *phi,
                               double u, const hub_hmc_params *params, const hub_solve_opts *opts,
                               hub_hmc_info *info, hipStream_t stream);
 
+/* One HMC update of each of nchain independent Markov chains on the same lattice,
+ * advanced through the same molecular-dynamics schedule in lockstep: every kick
+ * group solves the selected terms of all chains in one batch (small lattices, such
+ * as the 4-site benchmark of Sec. 7.2, fill the device only this way).  Each chain
+ * is updated exactly as by hub_hmc_trajectory with its own phi, pi, rho and u.
+ * phi, pi: device [nchain][N]; rho: device [nchain][n+1][N]; u, info: host
+ * [nchain].  Needs nchain * (n + 1) <= HUB_MAX_BATCH. */
+hub_status hub_hmc_trajectories(hub_ctx *ctx, const hub_lattice *lat, int32_t nchain, double *phi, double *pi,
+                                const hub_c128 *rho, const double *u, const hub_hmc_params *params,
+                                const hub_solve_opts *opts, hub_hmc_info *info, hipStream_t stream);
+
 /* Serving: one request = solve (M M^dagger + mu2) x = chi, then S = Re chi^dagger x and
  * dS/dphi, for its own lattice, phi and shift.  Requests are admitted by workspace
  * footprint against the budget as earlier ones retire and run batched with every

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOC
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
            "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
            "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
-           "hub_md_schedule", "hub_hmc_trajectory", "hub_solve_multishift", "hub_hasenbusch_masses"]
+           "hub_md_schedule", "hub_hmc_trajectory", "hub_hmc_trajectories", "hub_solve_multishift",
+           "hub_hasenbusch_masses"]
 
 
 class HubLattice(ctypes.Structure):
@@ -132,6 +133,9 @@ def load() -> ctypes.CDLL:
     L.hub_md_schedule.argtypes = [ctypes.POINTER(HubHmcParams), ctypes.POINTER(HubMdOp), i32, ctypes.POINTER(i32)]
     L.hub_hmc_trajectory.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, ctypes.POINTER(HubHmcParams),
                                      ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubHmcInfo), vp]
+    L.hub_hmc_trajectories.argtypes = [vp, ctypes.POINTER(HubLattice), i32, vp, vp, vp, ctypes.POINTER(dbl),
+                                       ctypes.POINTER(HubHmcParams), ctypes.POINTER(HubSolveOpts),
+                                       ctypes.POINTER(HubHmcInfo), vp]
     L.hub_solve_multishift.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
                                        ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo),
                                        ctypes.POINTER(dbl), vp]
@@ -348,6 +352,27 @@ def hub_hasenbusch_force(ctx: Context, lat: HubLattice, phi, mts, chi, terms=Non
     Sl = [S[i] if i in terms else None for i in range(n + 1)]
     il = [info[i].as_dict() if i in terms else None for i in range(n + 1)]
     return out, Sl, eta, il, st
+
+
+def hub_hmc_trajectories(ctx: Context, lat: HubLattice, phi, pi, rho, u, params: HubHmcParams,
+                         opts: HubSolveOpts | None = None, stream=None) -> list:
+    """One HMC update of each of nchain chains in lockstep: phi, pi float64 [nchain, ...],
+    rho complex128 [nchain, n+1, ...] (device), u a list of nchain uniforms.  Returns the
+    info dicts."""
+    n = _nsites(lat)
+    nc = len(u)
+    for t, what in ((phi, "phi"), (pi, "pi")):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != nc * n:
+            raise ValueError(f"{what} must be a contiguous float64 CUDA tensor with nchain * N entries")
+    if _vec(rho, lat, "rho") != nc * (params.n + 1):
+        raise ValueError("rho must hold nchain * (n+1) vectors")
+    uu = (ctypes.c_double * nc)(*[float(v) for v in u])
+    o = default_opts() if opts is None else opts
+    info = (HubHmcInfo * nc)()
+    _check(load().hub_hmc_trajectories(ctx.handle, ctypes.byref(lat), nc, phi.data_ptr(), pi.data_ptr(),
+                                       rho.data_ptr(), uu, ctypes.byref(params), ctypes.byref(o), info,
+                                       _stream(stream)))
+    return [i.as_dict(params.n) for i in info]
 
 
 def hub_solve_multishift(ctx: Context, lat: HubLattice, phi, mu2, b, x=None, opts: HubSolveOpts | None = None,

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhub.so")
-SOURCES = ["hub_kernels.hip", "hub_engine.hip", "hub_api.hip"]
+SOURCES = ["hub_kernels.hip", "hub_engine.hip", "hub_api.hip", "hub_hmc.hip", "hub_multishift.hip"]
 ARCH = os.environ.get("HUB_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.

@@ -15,12 +15,11 @@ Energies come from least-squares exponential fits of the mean correlator in the
 paper's windows (tau kappa in [0.2, 1] for Gamma, [0.6, 2] for M), with bootstrap
 errors over binned configurations.
 
-Independent Markov chains run in threads, one context and stream each, so their
-small launches overlap on the device.
+Independent Markov chains advance together through `hub_hmc_trajectories`, whose
+kick groups solve the terms of all chains in one batch: a 4-site system alone would
+leave the device idle.
 """
 from __future__ import annotations
-
-import threading
 
 import numpy as np
 import torch
@@ -73,38 +72,12 @@ def fit_energy(C, delta: float, window) -> float:
     return float(coef[1])
 
 
-def _chain(seed, lat, U_t, params, n_therm, n_meas, t0s, opts, out, idx, errors):
-    try:
-        ctx = hb.Context(0)
-        stream = torch.cuda.Stream()
-        rng = np.random.default_rng(seed)
-        shape = (lat.Nt, 2, lat.L1, lat.L2)
-        with torch.cuda.stream(stream):
-            phi = torch.from_numpy(rng.normal(0.0, np.sqrt(U_t), size=shape)).to("cuda")
-            acc, dH, samples = [], [], {"Gamma": [], "M": []}
-            for traj in range(n_therm + n_meas):
-                pi = torch.from_numpy(rng.standard_normal(size=shape)).to("cuda")
-                rho = (rng.standard_normal((params.n + 1,) + shape) + 1j * rng.standard_normal((params.n + 1,) + shape))
-                rho = torch.from_numpy(rho * np.sqrt(0.5)).to("cuda")
-                u = float(rng.uniform())
-                info = hb.hub_hmc_trajectory(ctx, lat, phi, pi, rho, u, params, opts=opts, stream=stream)
-                if traj >= n_therm:
-                    acc.append(info["accepted"])
-                    dH.append(info["dH"])
-                    m = measure(ctx, lat, phi, t0s, stream=stream)
-                    for k in samples:
-                        samples[k].append(m[k])
-        torch.cuda.synchronize()
-        ctx.close()
-        out[idx] = {"acc": acc, "dH": dH, "C": {k: np.array(v) for k, v in samples.items()}}
-    except Exception as e:  # reported by the caller
-        errors.append(repr(e))
-
-
-def run(Nt: int, n_chains: int = 8, n_therm: int = 50, n_meas: int = 200, U: float = 4.0, beta: float = 8.0,
+def run(Nt: int, n_chains: int = 32, n_therm: int = 50, n_meas: int = 200, U: float = 4.0, beta: float = 8.0,
         kappa: float = 1.0, n_md: int = 8, mass: float = 0.5, seed: int = 1, bin_size: int = 10,
-        n_boot: int = 200) -> dict:
-    """Ensembles at U/kappa, beta kappa on the 4-site lattice; returns energies with bootstrap errors."""
+        n_boot: int = 200, cold: bool = True) -> dict:
+    """Ensembles at U/kappa, beta kappa on the 4-site lattice: n_chains Markov chains (from
+    phi = 0 unless cold is False) updated together by `hub_hmc_trajectories`, measured
+    after every trajectory once thermalised; returns energies with bootstrap errors."""
     delta = beta / Nt
     lat = hb.lattice(2, 1, Nt, delta * kappa)
     U_t = delta * U
@@ -112,31 +85,43 @@ def run(Nt: int, n_chains: int = 8, n_therm: int = 50, n_meas: int = 200, U: flo
     opts = hb.default_opts(solver="cg", tol=1e-10)
     opts.use_x0 = 1
     t0s = list(range(0, Nt, max(1, Nt // 4)))
-    out = [None] * n_chains
-    errors = []
-    th = [threading.Thread(target=_chain, args=(seed * 1000 + c, lat, U_t, params, n_therm, n_meas, t0s, opts,
-                                                 out, c, errors)) for c in range(n_chains)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    if errors:
-        raise RuntimeError(errors[0])
-    res = {"Nt": Nt, "chains": n_chains, "trajectories_per_chain": n_therm + n_meas, "measured": n_chains * n_meas,
-           "acceptance": float(np.mean([a for o in out for a in o["acc"]])),
-           "mean_exp_minus_dH": float(np.mean([np.exp(-d) for o in out for d in o["dH"]]))}
+    shape = (Nt, 2, lat.L1, lat.L2)
     rng = np.random.default_rng(seed)
+    ctx = hb.Context(0)
+    try:
+        phi0 = np.zeros((n_chains,) + shape) if cold else rng.normal(0.0, np.sqrt(U_t), size=(n_chains,) + shape)
+        phi = torch.from_numpy(phi0).to("cuda")
+        acc, dH = [], []
+        samples = {"Gamma": [[] for _ in range(n_chains)], "M": [[] for _ in range(n_chains)]}
+        for traj in range(n_therm + n_meas):
+            pi = torch.from_numpy(rng.standard_normal(size=(n_chains,) + shape)).to("cuda")
+            rs = (n_chains, params.n + 1) + shape
+            rho = torch.from_numpy((rng.standard_normal(rs) + 1j * rng.standard_normal(rs)) * np.sqrt(0.5)).to("cuda")
+            u = rng.uniform(size=n_chains)
+            infos = hb.hub_hmc_trajectories(ctx, lat, phi, pi, rho, list(u), params, opts=opts)
+            if traj < n_therm:
+                continue
+            acc += [i["accepted"] for i in infos]
+            dH += [i["dH"] for i in infos]
+            for c in range(n_chains):
+                m = measure(ctx, lat, phi[c].contiguous(), t0s)
+                for k in samples:
+                    samples[k][c].append(m[k])
+    finally:
+        ctx.close()
+    res = {"Nt": Nt, "n_md": n_md, "chains": n_chains, "trajectories_per_chain": n_therm + n_meas,
+           "measured": n_chains * n_meas, "acceptance": float(np.mean(acc)),
+           "mean_exp_minus_dH": float(np.mean(np.exp(-np.array(dH))))}
     for name, win in WINDOWS.items():
         # bins of consecutive configurations within each chain
         bins = []
-        for o in out:
-            C = o["C"][name]
+        for c in range(n_chains):
+            C = np.array(samples[name][c])
             for b0 in range(0, len(C) - bin_size + 1, bin_size):
                 bins.append(C[b0:b0 + bin_size].mean(axis=0))
         bins = np.array(bins)
-        E = fit_energy(bins.mean(axis=0), delta, win)
+        res[f"E_{name}"] = fit_energy(bins.mean(axis=0), delta, win)
         boot = [fit_energy(bins[rng.integers(len(bins), size=len(bins))].mean(axis=0), delta, win)
                 for _ in range(n_boot)]
-        res[f"E_{name}"] = E
         res[f"E_{name}_err"] = float(np.nanstd(boot))
     return res

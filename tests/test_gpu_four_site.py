@@ -50,8 +50,8 @@ def test_free_field_energies(hub):
 
 
 def test_short_ensemble_runs():
-    r = four_site.run(32, n_chains=4, n_therm=5, n_meas=20, n_md=6, bin_size=5, n_boot=50)
-    assert r["measured"] == 80
+    r = four_site.run(32, n_chains=8, n_therm=5, n_meas=20, n_md=6, bin_size=5, n_boot=50)
+    assert r["measured"] == 160
     assert 0.3 < r["acceptance"] <= 1.0
     assert np.isfinite(r["E_Gamma"]) and np.isfinite(r["E_M"])
     assert 2.0 < r["E_Gamma"] < 5.0 and 0.5 < r["E_M"] < 3.0

@@ -148,3 +148,22 @@ def test_full_size_paper_schedule(hub):
     assert np.isfinite(info["dH"]) and abs(info["dH"]) < 50
     assert info["accepted"]
     assert float(torch.linalg.norm(pd - dev(phi))) > 1.0
+
+
+def test_batched_chains_equal_single_chain_updates(hub):
+    # every chain of a lockstep batch is updated bit for bit as it would be alone
+    hw = HASENBUSCH["hb_tiny"]
+    w = hw.base
+    hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+    p = hb.hmc_params(w.U_t, 4, hw.mts, [2, 1], traj_length=0.5)
+    ins = [draw_hmc(hw, seed=200 + c) for c in range(5)]
+    us = [0.3, 0.9, 0.0, 0.6, 0.99]
+    phi = torch.stack([dev(a[0]) for a in ins]).contiguous()
+    pi = torch.stack([dev(a[1]) for a in ins]).contiguous()
+    rho = torch.stack([dev(a[2]) for a in ins]).contiguous()
+    infos = hb.hub_hmc_trajectories(hub, hl, phi, pi, rho, us, p)
+    for c, (ph, q, r) in enumerate(ins):
+        pd, qd = dev(ph), dev(q)
+        one = hb.hub_hmc_trajectory(hub, hl, pd, qd, dev(r), us[c], p)
+        assert one == infos[c]
+        assert torch.equal(pd, phi[c]) and torch.equal(qd, pi[c])
