@@ -15,10 +15,12 @@ Further legs (not part of the step): the staggered-mass Hasenbusch split at the
 same lattice with the paper's tuned two masses (heat-bath, all-terms and per-term
 force evaluations), one full HMC trajectory with the paper's nested Omelyan
 schedule for that lattice, and the shared-Krylov multi-shift CG with its Lanczos
-spectral bounds against batched separate solves.
+spectral bounds against batched separate solves, and a short run of the 4-site
+benchmark (HMC ensembles in lockstep chains, quasi-particle energies against exact
+diagonalisation).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serving] [--no-hasenbusch] [--no-hmc]
-       [--no-multishift]
+       [--no-multishift] [--no-four-site]
 """
 from __future__ import annotations
 
@@ -56,6 +58,7 @@ def parse():
     ap.add_argument("--no-hasenbusch", action="store_true")
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-multishift", action="store_true")
+    ap.add_argument("--no-four-site", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     return ap.parse_args()
@@ -267,6 +270,8 @@ def main():
         out["hmc"] = hmc_run(ctx, hb, torch)
     if not args.no_multishift:
         out["multishift"] = multishift_run(ctx, hb, torch)
+    if not args.no_four_site:
+        out["four_site"] = four_site_run()
     if not args.no_serving:
         out["serving"] = serving_run(ctx, hb, torch, args.serving_requests)
     ctx.close()
@@ -407,6 +412,19 @@ def multishift_run(ctx, hb, torch, reps: int = 3) -> dict:
                     "hasenbusch_masses_eq_mu_i_n2": hb.hub_hasenbusch_masses(lam[0], lam[1], 2)})
         res[f"{w.L1}x{w.L2}x{w.Nt}"] = row
     return res
+
+
+def four_site_run() -> dict:
+    """The 4-site benchmark (2 x 1 cells, U/kappa = 4, beta kappa = 8, N_t = 64): 32 HMC
+    chains in lockstep with one Hasenbusch mass (0.5), 20 thermalisation and 60 measured
+    trajectories each; the Gamma and M energies against the exact values 3.429 and 1.565
+    (Table tab:fit results, the paper's N_t = 64 column: 3.555(16), 1.647(23))."""
+    from paper_1804_07195_amd import four_site
+    t0 = time.perf_counter()
+    r = four_site.run(64, n_chains=32, n_therm=20, n_meas=60, n_md=8, bin_size=10, n_boot=200)
+    r["seconds"] = round(time.perf_counter() - t0, 1)
+    r["exact"] = {"E_Gamma": 3.429, "E_M": 1.565}
+    return r
 
 
 def serving_run(ctx, hb, torch, nreq: int) -> dict:

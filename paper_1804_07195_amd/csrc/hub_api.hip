@@ -342,29 +342,33 @@ namespace api {
 
 hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_opts& o, hipStream_t stream) {
   Engine* eng = engine_for(ctx, stream);
-  // one single-precision copy per distinct phi for the mixed solver
-  std::map<const double*, float*> phi32;
+  // the phase e^{i phi} once per distinct phi (complex64 too for the mixed solver)
+  const bool want32 = o.solver == HUB_FGMRES_MIXED;
+  std::map<const double*, std::pair<double2*, float2*>> phase;
+  std::vector<void*> owned;
   hub_status result = HUB_OK;
-  if (o.solver == HUB_FGMRES_MIXED) {
-    for (System& sy : sys) {
-      if (phi32.count(sy.phi)) continue;
-      float* p = (float*)ctx->pool->alloc((size_t)sy.g.n * 4, stream);
-      if (!p) {
-        result = fail(HUB_ERR_OOM, "workspace for phi in single precision");
-        break;
-      }
-      phi32[sy.phi] = p;
-      const hipError_t e = launch_phi_to_f32(sy.phi, p, sy.g.n, stream);
-      if (e != hipSuccess) {
-        result = hip_fail(e, "phi conversion");
-        break;
-      }
+  for (System& sy : sys) {
+    if (phase.count(sy.phi)) continue;
+    double2* p64 = (double2*)ctx->pool->alloc((size_t)sy.g.n * 16, stream);
+    float2* p32 = want32 ? (float2*)ctx->pool->alloc((size_t)sy.g.n * 8, stream) : nullptr;
+    if (p64) owned.push_back(p64);
+    if (p32) owned.push_back(p32);
+    if (!p64 || (want32 && !p32)) {
+      result = fail(HUB_ERR_OOM, "workspace for the phase of phi");
+      break;
+    }
+    phase[sy.phi] = {p64, p32};
+    const hipError_t e = launch_phase(sy.phi, p64, p32, sy.g.n, stream);
+    if (e != hipSuccess) {
+      result = hip_fail(e, "phase");
+      break;
     }
   }
   size_t added = 0;
   for (System& sy : sys) {
     if (result != HUB_OK) break;
-    sy.phi32 = o.solver == HUB_FGMRES_MIXED ? phi32[sy.phi] : nullptr;
+    sy.ph64 = phase[sy.phi].first;
+    sy.ph32 = phase[sy.phi].second;
     sy.opts = o;
     if (!eng->add(&sy)) {
       result = fail(HUB_ERR_OOM, "solver workspace");
@@ -385,7 +389,7 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
     }
   }
   for (size_t k = 0; k < added; ++k) eng->remove(&sys[k]);
-  for (auto& kv : phi32) ctx->pool->release(kv.second, stream);
+  for (void* p : owned) ctx->pool->release(p, stream);
   hipError_t e = hipStreamSynchronize(stream);
   if (result != HUB_OK) return result;
   if (e != hipSuccess) return hip_fail(e, "solve");

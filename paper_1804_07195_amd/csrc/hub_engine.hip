@@ -299,16 +299,22 @@ bool Engine::add(System* s) {
       d.vec[S_Z0 + k] = get(n * 8);
       ok = ok && d.vec[S_Z0 + k];
     }
-    if (ok && !s->phi32) {
-      float* p32 = (float*)get(n * 4);
-      ok = ok && p32;
-      if (ok) {
-        if (launch_phi_to_f32(s->phi, p32, (int)n, st_) != hipSuccess) ok = false;
-        s->phi32 = p32;
-      }
-    }
-    d.phi32 = s->phi32;
   }
+  // the phase e^{i phi} of the solver kernels (shared with other systems when the
+  // caller precomputed it)
+  const bool want32 = is_fgmres(s->opts);
+  if (ok && (!s->ph64 || (want32 && !s->ph32))) {
+    double2* p64 = (double2*)get(n * 16);
+    float2* p32 = want32 ? (float2*)get(n * 8) : nullptr;
+    ok = ok && p64 && (!want32 || p32);
+    if (ok && launch_phase(s->phi, p64, p32, (int)n, st_) != hipSuccess) ok = false;
+    if (ok) {
+      s->ph64 = p64;
+      s->ph32 = p32;
+    }
+  }
+  d.ph64 = s->ph64;
+  d.ph32 = s->ph32;
   if (!ok) {
     for (void* p : s->owned) pool_->release(p, st_);
     s->owned.clear();

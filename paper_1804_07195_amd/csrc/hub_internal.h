@@ -73,7 +73,8 @@ struct SysDesc {
   Geom g;
   double mu2;
   const double* phi;     // float64 phi [n]
-  const float* phi32;    // float32 copy of phi [n] (single-precision path)
+  const double2* ph64;   // (cos phi, sin phi) [n], FP64 solver kernels
+  const float2* ph32;    // the same in complex64 [n] (single-precision path)
   Scal* sc;
   double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
   double* part1;         // per-tile partials of CG stage 1 [ntiles]
@@ -99,7 +100,7 @@ struct MsScal {
 };
 struct MsDesc {
   Geom g;
-  const double* phi;
+  const double2* ph64;        // (cos phi, sin phi) per site
   double mu2;                 // shift of the base system
   const double2* b;
   double2* x;                 // base solution
@@ -169,7 +170,8 @@ hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, co
                         const double2* sub = nullptr);
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
                          double* result, hipStream_t st);
-hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st);
+// p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, rounded to complex64.
+hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st);
 // phi += eps pi;  pi -= G + cg phi (G may be NULL).
 hipError_t launch_md_drift(double* phi, const double* pi, double eps, int n, hipStream_t st);
 hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double cg, int n, hipStream_t st);
@@ -187,7 +189,8 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
 hipError_t launch_ms_start(const MsDesc* d, int ntiles, hipStream_t st);
 hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st);
 // Algorithmic bytes per site of each CG stage (reads + writes of distinct vectors).
-constexpr double kCgBytes[2][2] = {{72.0, 104.0}, {36.0, 52.0}};  // [single][stage-1]
+// The phase e^{i phi} is read precomputed: 16 bytes per site in FP64, 8 in complex64.
+constexpr double kCgBytes[2][2] = {{80.0, 112.0}, {40.0, 56.0}};  // [single][stage-1]
 // u = M^dagger in; in is an FP64 slot or (in_c64) a C64 slot; u is S_U.
 hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st);
 // Every reduction below leaves per-tile partials; a finalisation kernel (one

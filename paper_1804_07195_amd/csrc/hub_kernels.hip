@@ -25,6 +25,10 @@ namespace hub {
 namespace {
 
 // Sites whose loads are issued together (per thread) in the stencil kernels.
+// Site pairs of the complex64 pair path whose loads are in flight together.
+#ifndef HUB_PAIRS_PER_ROUND
+#define HUB_PAIRS_PER_ROUND 2
+#endif
 #ifndef HUB_SPT64
 #define HUB_SPT64 (HUB_SITES_PER_THREAD < 2 ? HUB_SITES_PER_THREAD : 2)
 #endif
@@ -127,6 +131,41 @@ template <typename T> struct Real {
   __device__ __forceinline__ hub_f2v pair(int k) const { return ((HUB_GAS hub_f2v*)p)[k >> 1]; }
 };
 
+// The phase e^{i phi} a stencil needs, from one of two sources:
+//  * AnglePhi - phi itself; cos and sin are computed per site (the public operator
+//               kernels, whose input is phi);
+//  * PhasePhi - (cos phi, sin phi) precomputed once per solve (the solver kernels:
+//               a 16- or 8-byte load replaces a sincos per site).
+// load(k) returns the raw value of site k, cs() turns it into (cos, sin); load2 / cs2
+// do the same for the two sites k, k+1 (k even) of the complex64 pair path.
+template <typename R> struct AnglePhi {
+  Real<R> a;
+  using Raw = R;
+  using Raw2 = hub_f2v;
+  __device__ __forceinline__ explicit AnglePhi(const void* q) : a(q) {}
+  __device__ __forceinline__ Raw load(int k) const { return a[k]; }
+  __device__ __forceinline__ void cs(Raw v, R& c, R& s) const { phase_cs(v, c, s); }
+  __device__ __forceinline__ Raw2 load2(int k) const { return a.pair(k); }
+  __device__ __forceinline__ void cs2(Raw2 v, int h, float& c, float& s) const { phase_cs(h ? v.y : v.x, c, s); }
+};
+template <typename R> struct PhasePhi {
+  using C = typename V2<R>::T;
+  Vec<C> p;
+  using Raw = C;
+  using Raw2 = C64x2;
+  __device__ __forceinline__ explicit PhasePhi(const void* q) : p(q) {}
+  __device__ __forceinline__ Raw load(int k) const { return p[k]; }
+  __device__ __forceinline__ void cs(Raw v, R& c, R& s) const {
+    c = v.x;
+    s = v.y;
+  }
+  __device__ __forceinline__ Raw2 load2(int k) const { return p.pair(k); }
+  __device__ __forceinline__ void cs2(Raw2 v, int h, float& c, float& s) const {
+    c = h ? v.b.x : v.a.x;
+    s = h ? v.b.y : v.a.y;
+  }
+};
+
 // The stencil of M (DAG = false) or M^dagger (DAG = true) at site n (eq. (ferm_op) and its
 // conjugate transpose):
 //   M,  A row: -x(n) + s (e^{ i phi(n)}  - m) x(t-1) - kappa sum_bonds x_B
@@ -177,10 +216,8 @@ __device__ __forceinline__ SiteIdx site_index(const Geom& g, int n) {
 }
 
 template <typename R, bool DAG, typename C>
-__device__ __forceinline__ C stencil_combine(const Geom& g, const SiteIdx& st, R ph, C xs, C xt, C x0, C x1,
+__device__ __forceinline__ C stencil_combine(const Geom& g, const SiteIdx& st, R c, R s, C xs, C xt, C x0, C x1,
                                              C x2) {
-  R c, s;
-  phase_cs(ph, c, s);
   const R sgn = st.wrap ? R(-1) : R(1);
   const R es = (st.isA != DAG) ? s : -s;
   const R cr = sgn * (c - (R)g.ms), ci = sgn * es;
@@ -222,7 +259,7 @@ __device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int
       st[m] = site_index<DAG>(g, n);
     }
     RW xs[SPT], xt[SPT], x0[SPT], x1[SPT], x2[SPT];
-    R ph[SPT];
+    typename Phi::Raw ph[SPT];
     PV pv[SPT];
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
@@ -231,14 +268,16 @@ __device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int
       x0[m] = ld(st[m].h0);
       x1[m] = ld(st[m].h1);
       x2[m] = ld(st[m].h2);
-      ph[m] = (R)phi[st[m].pn];
+      ph[m] = phi.load(st[m].pn);
       pv[m] = pre(st[m].n);
     }
     if (r0 == 0 && !mid()) return;
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const C s0 = cook(xs[m]);
-      const C y = stencil_combine<R, DAG>(g, st[m], ph[m], s0, cook(xt[m]), cook(x0[m]), cook(x1[m]),
+      R c, s;
+      phi.cs(ph[m], c, s);
+      const C y = stencil_combine<R, DAG>(g, st[m], c, s, s0, cook(xt[m]), cook(x0[m]), cook(x1[m]),
                                           cook(x2[m]));
       if (ok[m]) post(st[m].n, y, s0, pv[m]);
     }
@@ -314,19 +353,23 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
   using PV = decltype(pre(0));
   using R2 = decltype(ld2(0));
   using R1 = decltype(ld1(0));
-  constexpr int NP = kSitesPerThread / 2;
+  constexpr int NPT = kSitesPerThread / 2;  // pairs per thread
+  constexpr int NP = HUB_PAIRS_PER_ROUND < NPT ? HUB_PAIRS_PER_ROUND : NPT;  // pairs in flight per round
+  static_assert(NPT % NP == 0, "rounds must divide the pairs");
+#pragma unroll
+  for (int q0 = 0; q0 < NPT; q0 += NP) {
   PairIdx st[NP];
   bool ok[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    int n = tile * kTile + 2 * (threadIdx.x + m * kBlock);
+    int n = tile * kTile + 2 * (threadIdx.x + (q0 + m) * kBlock);
     ok[m] = n < g.n;
     n = ok[m] ? n : g.n - 2;
     st[m] = pair_index<DAG>(g, n);
   }
   R2 rs[NP], rt[NP], r0[NP], r1[NP];
   R1 re[NP];
-  hub_f2v ph[NP];
+  typename Phi::Raw2 ph[NP];
   PV pv[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
@@ -335,10 +378,10 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
     r0[m] = ld2(st[m].h0);
     r1[m] = ld2(st[m].h1);
     re[m] = ld1(st[m].hx);
-    ph[m] = phi.pair(DAG ? st[m].tn : st[m].n);
+    ph[m] = phi.load2(DAG ? st[m].tn : st[m].n);
     pv[m] = pre(st[m].n);
   }
-  if (!mid()) return;
+  if (q0 == 0 && !mid()) return;
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
     const PairIdx& sm = st[m];
@@ -364,7 +407,7 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
     C64x2 y;
     {
       float c, s;
-      phase_cs(ph[m].x, c, s);
+      phi.cs2(ph[m], 0, c, s);
       const float es = plus ? s : -s;
       const float cr = sgn * (c - mst), ci = sgn * es;
       const float tr = cr * xt.a.x - ci * xt.a.y, ti = cr * xt.a.y + ci * xt.a.x;
@@ -373,7 +416,7 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
     }
     {
       float c, s;
-      phase_cs(ph[m].y, c, s);
+      phi.cs2(ph[m], 1, c, s);
       const float es = plus ? s : -s;
       const float cr = sgn * (c - mst), ci = sgn * es;
       const float tr = cr * xt.b.x - ci * xt.b.y, ti = cr * xt.b.y + ci * xt.b.x;
@@ -381,6 +424,7 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
       y.b.y = sig * (xs.b.y - ti) - kap * b1.y;
     }
     if (ok[m]) post(sm.n, y, xs, pv[m]);
+  }
   }
 }
 
@@ -419,9 +463,13 @@ __device__ __forceinline__ int find_sys(const LaunchList& L, int lt) {
   return lo;
 }
 
-template <typename PhiT> __device__ __forceinline__ Real<PhiT> phi_of(const SysDesc* d);
-template <> __device__ __forceinline__ Real<double> phi_of<double>(const SysDesc* d) { return Real<double>(d->phi); }
-template <> __device__ __forceinline__ Real<float> phi_of<float>(const SysDesc* d) { return Real<float>(d->phi32); }
+template <typename R> __device__ __forceinline__ PhasePhi<R> phase_of(const SysDesc* d);
+template <> __device__ __forceinline__ PhasePhi<double> phase_of<double>(const SysDesc* d) {
+  return PhasePhi<double>(d->ph64);
+}
+template <> __device__ __forceinline__ PhasePhi<float> phase_of<float>(const SysDesc* d) {
+  return PhasePhi<float>(d->ph32);
+}
 
 __device__ __forceinline__ int load_active(Scal* sc) {
   return __hip_atomic_load(&sc->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -449,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   auto ld = [=](int k) { return xb[k]; };
   auto pre = [](int) { return NoPre{}; };
   auto post = [=](int n, double2 v, double2, NoPre) { yb[n] = v; };
-  stencil_sites<double, DAG, kPubSites, kPubSites>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+  stencil_sites<double, DAG, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{}, post);
 }
 
 struct Mu2Arr { double v[kMaxSys]; };
@@ -470,7 +518,8 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
     q.y += m2 * xv.y;
     y[off + n] = q;
   };
-  stencil_sites<double, false, kPubSites, kPubSites>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+  stencil_sites<double, false, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{},
+                                                     post);
 }
 
 // dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} z(t-1)],
@@ -552,10 +601,23 @@ __global__ __launch_bounds__(kBlock) void k_dot_finish(const double* __restrict_
   if (threadIdx.x == 0) result[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_phi_to_f32(const double* __restrict__ phi, float* __restrict__ p32,
-                                                       int n) {
+// (cos phi, sin phi) per site in FP64, and rounded to complex64 when p32 is given.
+__global__ __launch_bounds__(kBlock) void k_phase(const double* __restrict__ phi, double2* __restrict__ p64,
+                                                  float2* __restrict__ p32, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p32[i] = (float)phi[i];
+  if (i >= n) return;
+  double c, s;
+  sincos(phi[i], &s, &c);
+  double2 v;
+  v.x = c;
+  v.y = s;
+  p64[i] = v;
+  if (p32) {
+    float2 w;
+    w.x = (float)c;
+    w.y = (float)s;
+    p32[i] = w;
+  }
 }
 
 // Molecular dynamics (Sec. 5.2): phi += eps pi (T_pi), and the momentum kick
@@ -604,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
   const int it = L.it[kk];
   const R mu2 = (R)d->mu2;
   const Vec<C> r(d->vec[sR]), po(d->vec[sP + (it & 1)]), pn(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]);
-  const Real<PhiT> phi = phi_of<PhiT>(d);
+  const PhasePhi<R> phi = phase_of<R>(d);
   R beta = 0;
   bool stopped = false;  // same value in every thread of every workgroup of the system
   // |r_it|^2, the stopping test and beta, once the stencil loads are in flight
@@ -707,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
   };
   const R mu2 = (R)d->mu2;
   const Vec<C> p(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]), x(d->vec[L.pi[kk]]), r(d->vec[sR]);
-  const Real<PhiT> phi = phi_of<PhiT>(d);
+  const PhasePhi<R> phi = phase_of<R>(d);
   struct Own {
     C p, x, r;
   };
@@ -834,7 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
   const double mu2 = d->mu2;
   const int ns = d->ns;
   const Vec<double2> r(d->r), po(d->p[it & 1]), pn(d->p[1 - (it & 1)]), u(d->u);
-  const Real<double> phi(d->phi);
+  const PhasePhi<double> phi(d->ph64);
   __shared__ double s_as[kMsMax], s_bs[kMsMax], s_zn[kMsMax];
   __shared__ int s_live[kMsMax];
   double beta = 0.0;
@@ -952,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_ms2(const MsDesc* __restrict__ d, in
     return true;
   };
   const Vec<double2> p(d->p[1 - (it & 1)]), u(d->u), x(d->x), r(d->r);
-  const Real<double> phi(d->phi);
+  const PhasePhi<double> phi(d->ph64);
   struct Own {
     double2 p, x, r;
   };
@@ -992,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_mdag_slot(const SysDesc* __restrict_
   (void)sc;
   const Vec<Tin> in(d->vec[s_in]);
   const Vec<double2> u(d->vec[S_U]);
-  const Real<double> phi = phi_of<double>(d);
+  const PhasePhi<double> phi = phase_of<double>(d);
   auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
   auto pre = [](int) { return NoPre{}; };
   auto post = [=](int n, double2 v, double2, NoPre) { u.set(n, v); };
@@ -1015,7 +1077,7 @@ __global__ __launch_bounds__(kBlock) void k_normal2_slot(const SysDesc* __restri
   const Vec<Tin> in(d->vec[s_in]);
   const bool has_b = s_b >= 0;
   const Vec<double2> bv(has_b ? d->vec[s_b] : nullptr), u(d->vec[S_U]), out(d->vec[s_out]);
-  const Real<double> phi = phi_of<double>(d);
+  const PhasePhi<double> phi = phase_of<double>(d);
   const double mu2 = d->mu2;
   auto ld = [=](int k) { return u[k]; };
   struct Own {
@@ -1295,8 +1357,8 @@ hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_phi_to_f32(const double* phi, float* phi32, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_phi_to_f32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, phi32, n);
+hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_phase, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, p64, p32, n);
   return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   const int ns = nshift - 1;
   const int maxit = o.max_iter;
   // workspace: r, p pair, u, the shifted directions, partials, scalars, descriptor, Lanczos history
-  const size_t vecs = (size_t)(4 + ns) * N * 16;
+  const size_t vecs = (size_t)(5 + ns) * N * 16;  // r, p pair, u, the phase, shifted directions
   const size_t parts = 2 * (size_t)nt * sizeof(double);
   const size_t hist_bytes = (2 * (size_t)maxit + 2) * sizeof(double);
   const size_t tail = ((sizeof(MsScal) + 255) / 256) * 256 + ((sizeof(MsDesc) + 255) / 256) * 256;
@@ -89,7 +89,7 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   MsDesc h;
   std::memset(&h, 0, sizeof(h));
   h.g = g;
-  h.phi = phi;
+  h.ph64 = v + (size_t)(4 + ns) * N;
   h.mu2 = mu2[bi];
   h.b = (const double2*)b;
   h.x = (double2*)x + bi * N;
@@ -119,7 +119,8 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   int iters = 0;
   std::vector<double> hist;
   do {
-    hipError_t e = hipMemcpyAsync(dd, &h, sizeof(h), hipMemcpyHostToDevice, stream);
+    hipError_t e = launch_phase(phi, const_cast<double2*>(h.ph64), nullptr, (int)N, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dd, &h, sizeof(h), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_ms_start(dd, nt, stream);
     if (e != hipSuccess) {
       result = hip_fail(e, "multi-shift start");
