@@ -11,7 +11,7 @@ namespace hub {
 
 constexpr int kBlock = 256;                   // threads per workgroup (4 wave64)
 #ifndef HUB_SITES_PER_THREAD
-#define HUB_SITES_PER_THREAD 4
+#define HUB_SITES_PER_THREAD 8
 #endif
 constexpr int kSitesPerThread = HUB_SITES_PER_THREAD;  // sites handled by each thread
 constexpr int kTile = kBlock * kSitesPerThread;  // sites per workgroup tile

@@ -24,8 +24,11 @@
 namespace hub {
 namespace {
 
-// Sites whose loads are issued together (per thread) in the stencil kernels.
-// Site pairs of the complex64 pair path whose loads are in flight together.
+// Loads in flight per thread in the stencil kernels: site pairs of the complex64
+// pair path, and sites of the generic path in FP64 and complex64.  With 8 sites
+// per thread (2048-site tiles) a 102x102x64 system is 651 workgroups, resident in
+// one round at the register use these give; more loads per round would cost
+// occupancy, fewer would expose latency.
 #ifndef HUB_PAIRS_PER_ROUND
 #define HUB_PAIRS_PER_ROUND 2
 #endif
@@ -33,7 +36,7 @@ namespace {
 #define HUB_SPT64 (HUB_SITES_PER_THREAD < 2 ? HUB_SITES_PER_THREAD : 2)
 #endif
 #ifndef HUB_SPT32
-#define HUB_SPT32 (HUB_SITES_PER_THREAD < 4 ? HUB_SITES_PER_THREAD : 4)
+#define HUB_SPT32 (HUB_SITES_PER_THREAD < 2 ? HUB_SITES_PER_THREAD : 2)
 #endif
 template <typename R> struct Spt;
 template <> struct Spt<double> { static constexpr int v = HUB_SPT64; };
