@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-hmc", action="store_true")
     ap.add_argument("--no-multishift", action="store_true")
     ap.add_argument("--no-four-site", action="store_true")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="target for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then one "
+                         "step and nothing else")
     ap.add_argument("--serving-requests", type=int, default=120)
     ap.add_argument("--cpu-budget-s", type=float, default=25.0)
     return ap.parse_args()
@@ -112,6 +115,34 @@ def _oracle_worker(args):
             "sec_per_iter": dt / max(it, 1), "seconds": dt}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg2_c64_102x102x64.md")
+TRAFFIC_SOURCES = ["paper_1804_07195_amd/csrc/hub_kernels.hip", "paper_1804_07195_amd/csrc/hub_internal.h",
+                   "paper_1804_07195_amd/csrc/hub_engine.hip", "paper_1804_07195_amd/csrc/hub_engine.h"]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE counter runs,
+    or None when the kernel or engine sources changed since they were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    vals = {}
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 2 and parts[0] == "source_sha256":
+            vals["sha"] = parts[1]
+        elif len(parts) == 3 and parts[0] == "traffic_bytes_per_launch":
+            vals[parts[1]] = float(parts[2])
+    if vals.get("sha") != h.hexdigest():
+        return None
+    return vals.get(kernel)
+
+
 def cpu_baseline(wname: str, budget: float) -> dict:
     w = WORKLOADS[wname]
     with mp.get_context("spawn").Pool(w.batch) as pool:
@@ -136,6 +167,8 @@ def main():
               f"note, not built", file=sys.stderr)
         sys.exit(2)
 
+    if args.counter_run:
+        args.steps, args.warmup, args.no_cpu = 1, 0, True
     # The CPU baseline runs first, in worker processes started before this process
     # touches the GPU.
     cpu = None if args.no_cpu else cpu_baseline("large2", args.cpu_budget_s)
@@ -145,6 +178,14 @@ def main():
     from paper_1804_07195_amd import binding as hb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.counter_run:
+        # counter calibration: 256 MiB read + 256 MiB written by a plain copy kernel
+        a = torch.ones(16 << 20, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = WORKLOADS["large2"]
     hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
     ctx = hb.Context(0)
@@ -173,6 +214,9 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if args.counter_run:
+        print(json.dumps({"counter_run": True, "ms_per_step": 1e3 * elapsed}), flush=True)
+        return
     # Kernel timing pass: the same steps again with every CG-kernel launch bound to
     # HIP start/stop events on the solver's stream (kept out of the timed region
     # above, whose throughput the per-launch events would lower).
@@ -192,8 +236,10 @@ def main():
     # dominant kernel of the step (largest summed time among the timed CG kernels)
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom["GBps"]
+    traffic = measured_traffic(dom_name)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": None if traffic is None else round(traffic),
                 "avg_launch_us": round(dom["avg_us"], 3), "launches": dom["launches"],
                 "timed_over": f"{prof_steps} steps after the timed region, HIP events bound to every launch",
                 "alg_bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1))}

@@ -49,6 +49,9 @@ class Pool {
   mutable std::mutex mu_;
 };
 
+// Block length (CG iterations between flag reads) near a system's expected end.
+constexpr int kTailBlock = 4;
+
 // Host-side state of one linear system (M M^dagger + mu2) x = b.
 struct System {
   // inputs
@@ -73,6 +76,7 @@ struct System {
   int cg_total = 0;     // FP64 CG iterations over all restarts
   int enq = 0;          // CG iterations enqueued since the last CG setup
   int gen = 0;          // number of CG setups so far (tags in-flight blocks)
+  int pred = 0;         // iterations of the system's previous CG run (0: none yet)
   double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
   std::vector<std::complex<double>> H;  // (m+1) x m, column-major
   std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload

@@ -616,7 +616,11 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     if (!s || s->done) continue;
     if ((single && s->phase == PH_F_INNER) || (!single && s->phase == PH_CG_ITER)) {
       v.push_back(s);
-      k = std::min(k, std::max(1, s->opts.check_every));
+      int ks = std::max(1, s->opts.check_every);
+      // near the iteration count of the system's previous CG run, enqueue short
+      // blocks: launches after convergence return at once but still cost a launch
+      if (s->pred > 0 && s->enq + ks > s->pred - kTailBlock) ks = std::min(ks, kTailBlock);
+      k = std::min(k, ks);
     }
   }
   if (v.empty()) return hipSuccess;
@@ -702,6 +706,7 @@ hipError_t Engine::finish_block(Block& b) {
     if (s->done || !want || s->gen != b.gen[q]) continue;
     const Scal& sc = flags[s->slot];
     if (sc.active) continue;
+    s->pred = sc.iters;
     if (single) {
       s->info.inner_iters += sc.iters;
       s->phase = s->post;
