@@ -325,11 +325,12 @@ hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* 
   }
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
-  void* u = ctx->pool->alloc((size_t)batch * g.n * 16, stream);
-  if (!u) return HUB_ERR_OOM;
-  hipError_t e = launch_apply(g, phi, (const double2*)x, (double2*)u, batch, true, stream);
-  if (e == hipSuccess)
-    e = launch_normal2(g, phi, m2, (const double2*)u, (const double2*)x, (double2*)y, batch, stream);
+  // two passes, u = M^dagger x then y = M u + mu2 x: faster here than the one-pass
+  // 12-point form, whose extra neighbour loads cost more than the bytes it saves
+  double2* u = (double2*)ctx->pool->alloc((size_t)batch * g.n * 16, stream);
+  if (!u) return fail(HUB_ERR_OOM, "workspace for M^dagger x");
+  hipError_t e = launch_apply(g, phi, (const double2*)x, u, batch, true, stream);
+  if (e == hipSuccess) e = launch_normal2(g, phi, m2, u, (const double2*)x, (double2*)y, batch, stream);
   ctx->pool->release(u, stream);
   if (e != hipSuccess) return hip_fail(e, "normal operator launch");
   return HUB_OK;

@@ -419,11 +419,10 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
           HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
           HUB_TRY(read_scal({s}));
           s->bb = h_scal_[s->slot].red[0];
-          HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
           L.pa[0] = tol * tol * s->bb;
           L.pr[0] = 0.0;
           L.pi[0] = o.max_iter;
-          HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+          HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
           s->info.applies++;
         }
         s->enq = 0;
@@ -440,8 +439,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
         s->err = std::sqrt(s->bb);
       } else {
         HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
-        HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
-        HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 2, st_));
+        HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 2, st_));
         HUB_TRY(read_scal({s}));
         s->bb = h_scal_[s->slot].red[0];
         s->err = std::sqrt(h_scal_[s->slot].red[2]);
@@ -477,11 +475,10 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
     case PH_CG_CONFIRM: {
       progressed = true;
       LaunchList L = one(s);
-      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
       L.pa[0] = tol * tol * s->bb;
       L.pr[0] = 0.0;
       L.pi[0] = std::max(1, o.max_iter - s->cg_total);
-      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+      HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
       s->info.applies++;
       HUB_TRY(read_scal({s}));
       const double rr = h_scal_[s->slot].red[1];
@@ -504,8 +501,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       HUB_TRY(upload_y(s, y));
       LaunchList L = one(s);
       HUB_TRY(launch_xupdate(d_desc_, L, 1, !o.use_x0, st_));
-      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
-      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
+      HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
       s->info.applies++;
       HUB_TRY(read_scal({s}));
       s->err = std::sqrt(h_scal_[s->slot].red[0]);
@@ -554,8 +550,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       const int j = s->j;
       const int m = o.restart_m;
       LaunchList L = one(s);
-      HUB_TRY(launch_mdag_slot(d_desc_, L, S_Z0 + j, true, st_));
-      HUB_TRY(launch_normal2_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
+      HUB_TRY(launch_normal_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
       HUB_TRY(launch_multidot(d_desc_, L, S_R, S_V0, j + 1, 0, st_));
       HUB_TRY(launch_cgs(d_desc_, L, S_R, S_V0, j + 1, 0, 2 * (j + 1), st_));
       s->info.applies++;
@@ -580,8 +575,7 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
         HUB_TRY(upload_y(s, y));
         HUB_TRY(launch_xupdate(d_desc_, L, k, false, st_));
       }
-      HUB_TRY(launch_mdag_slot(d_desc_, L, S_X, false, st_));
-      HUB_TRY(launch_normal2_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
+      HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
       s->info.applies++;
       s->cycles++;
       s->info.outer_iters = s->cycles;

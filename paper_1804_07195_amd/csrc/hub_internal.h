@@ -162,8 +162,6 @@ enum RedMode : int {
 // ---------------------------------------------------------------------------
 hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch,
                         bool dag, hipStream_t st);
-hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
-                          const double2* x, double2* y, int batch, hipStream_t st);
 // out (+)= scale dS/dphi for eta and xi (minus `sub` when given: Hasenbusch ratio terms).
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi,
                         double scale, int accumulate, double* out, int batch, hipStream_t st,
@@ -172,6 +170,9 @@ hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int 
                          double* result, hipStream_t st);
 // p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, rounded to complex64.
 hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st);
+// y_b = M u_b + mu2_b x_b (the second pass of the public normal operator, u = M^dagger x).
+hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
+                          const double2* x, double2* y, int batch, hipStream_t st);
 // phi += eps pi;  pi -= G + cg phi (G may be NULL).
 hipError_t launch_md_drift(double* phi, const double* pi, double eps, int n, hipStream_t st);
 hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double cg, int n, hipStream_t st);
@@ -191,14 +192,13 @@ hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st);
 // Algorithmic bytes per site of each CG stage (reads + writes of distinct vectors).
 // The phase e^{i phi} is read precomputed: 16 bytes per site in FP64, 8 in complex64.
 constexpr double kCgBytes[2][2] = {{80.0, 112.0}, {40.0, 56.0}};  // [single][stage-1]
-// u = M^dagger in; in is an FP64 slot or (in_c64) a C64 slot; u is S_U.
-hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st);
 // Every reduction below leaves per-tile partials; a finalisation kernel (one
 // workgroup per system) sums them in a fixed order into sc->red[red_off..] and,
 // with RED_CG_SETUP, starts a CG on the result (pa, pr, pi of the launch list).
-// out = [b -] (M u + mu2 in), |out|^2 (mode RED_NONE: no reduction).
-hipError_t launch_normal2_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b,
-                               int s_out, RedMode mode, int red_off, hipStream_t st);
+// out = [b -] (M M^dagger + mu2) in, in one pass of the 12-point form (in: an FP64
+// slot or, with in_c64, a complex64 slot), |out|^2 (mode RED_NONE: no reduction).
+hipError_t launch_normal_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b, int s_out,
+                              RedMode mode, int red_off, hipStream_t st);
 // x = 0, r = b, |b|^2 -> red[0]; with RED_CG_SETUP also the FP64 CG start.
 hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, RedMode mode, hipStream_t st);
 // red[off + 2i, 2i+1] = <v_i, w>, i < cnt.

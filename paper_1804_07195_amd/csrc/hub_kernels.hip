@@ -505,6 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
 
 struct Mu2Arr { double v[kMaxSys]; };
 
+// y_b = M u_b + mu2_b x_b: the second pass of the public normal operator (u = M^dagger x).
 __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __restrict__ phi, Mu2Arr mu2,
                                                         const double2* __restrict__ u,
                                                         const double2* __restrict__ x, double2* __restrict__ y,
@@ -1050,19 +1051,8 @@ template <> __device__ __forceinline__ double2 to_c128<float2>(float2 v) {
   return o;
 }
 
-// u = M^dagger in (FP64 arithmetic; in is FP64 or C64).
-template <typename Tin>
-__global__ __launch_bounds__(kBlock) void k_mdag_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in) {
-  HUB_PROLOGUE
-  (void)sc;
-  const Vec<Tin> in(d->vec[s_in]);
-  const Vec<double2> u(d->vec[S_U]);
-  const PhasePhi<double> phi = phase_of<double>(d);
-  auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
-  auto pre = [](int) { return NoPre{}; };
-  auto post = [=](int n, double2 v, double2, NoPre) { u.set(n, v); };
-  stencil_sites<double, true, Spt<double>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
-}
+
+
 
 __device__ __forceinline__ void store_partials(const SysDesc* d, int tile, const double* vals, int nv) {
   if (threadIdx.x == 0) {
@@ -1071,38 +1061,132 @@ __device__ __forceinline__ void store_partials(const SysDesc* d, int tile, const
   }
 }
 
-// out = [b -] (M u + mu^2 in), partial of |out|^2 unless mode == RED_NONE.
+// ---------------------------------------------------------------------------
+// The normal operator A = M M^dagger + mu2 in one pass.  From eq. (ferm_op), with
+// c_A(t) = s(t) (e^{i phi_A(t)} - m) and c_B(t) = s'(t) (e^{-i phi_B(t)} - m) (s = -1
+// on the A hop out of t = 0, s' = -1 on the B hop out of t = N_t - 1), the same-slice
+// A-B terms of M M^dagger cancel and each row has 12 entries:
+//   A(t): (1 + |c_A(t)|^2 + 3 kappa^2 + mu2) x - c_A(t) x_A(t-1) - conj(c_A(t+1)) x_A(t+1)
+//         + kappa^2 sum_6 x_A(t) - kappa sum_b (c_A(t) - conj(c_B(t-1)[b])) x_B(t-1)[b]
+//   B(t): (1 + |c_B(t)|^2 + 3 kappa^2 + mu2) x - c_B(t) x_B(t+1) - conj(c_B(t-1)) x_B(t-1)
+//         + kappa^2 sum_6 x_B(t) - kappa sum_a (conj(c_A(t+1)[a]) - c_B(t)) x_A(t+1)[a]
+// where sum_6 runs over the second neighbours (i, j) + {(1,0), (0,1), (-1,0), (-1,1),
+// (0,-1), (1,-1)} (the A-B-A and B-A-B paths; wrapped offsets that coincide add,
+// exactly as the paths do) and b / a over the three bonds of the site (at slice
+// t-1 for A rows, t+1 for B rows).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  double2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) b
+  double2 r;
+  r.x = a.x * b.x + a.y * b.y;
+  r.y = a.x * b.y - a.y * b.x;
+  return r;
+}
+
+template <typename Load>
+__device__ __forceinline__ double2 normal12(const Geom& g, const PhasePhi<double>& ph, int n, double mu2, Load ld) {
+  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
+  const int j = n - (int)q1 * g.L2;
+  const uint32_t q2 = fdiv(q1, g.dL1);
+  const int i = (int)q1 - (int)q2 * g.L1;
+  const bool isA = (q2 & 1u) == 0;
+  const int t = (int)(q2 >> 1);
+  const int P = g.P, L1 = g.L1, L2 = g.L2;
+  const int tp = (t + 1 == g.Nt) ? 0 : t + 1, tm = (t == 0) ? g.Nt - 1 : t - 1;
+  const int ip = (i + 1 == L1) ? 0 : i + 1, im = (i == 0) ? L1 - 1 : i - 1;
+  const int jp = (j + 1 == L2) ? 0 : j + 1, jm = (j == 0) ? L2 - 1 : j - 1;
+  const int r0 = i * L2, rp = ip * L2, rm = im * L2;
+  const int own = n;
+  const int pA = 2 * t * P, pB = pA + P;                // planes of slice t
+  const int here = isA ? pA : pB;
+  // same sublattice at t-1, t+1
+  const int nm = (isA ? 2 * tm * P : 2 * tm * P + P) + r0 + j;
+  const int np = (isA ? 2 * tp * P : 2 * tp * P + P) + r0 + j;
+  // opposite sublattice: A rows take B at t-1 (bonds (i,j), (i-1,j), (i,j-1));
+  // B rows take A at t+1 (bonds (i,j), (i+1,j), (i,j+1))
+  const int ob = isA ? 2 * tm * P + P : 2 * tp * P;
+  const int b0 = ob + r0 + j;
+  const int b1 = isA ? ob + rm + j : ob + rp + j;
+  const int b2 = isA ? ob + r0 + jm : ob + r0 + jp;
+  const double2 xs = ld(own), xm = ld(nm), xp = ld(np);
+  const double2 s0 = ld(here + rp + j), s1 = ld(here + r0 + jp), s2 = ld(here + rm + j);
+  const double2 s3 = ld(here + rm + jp), s4 = ld(here + r0 + jm), s5 = ld(here + rp + jm);
+  const double2 y0 = ld(b0), y1 = ld(b1), y2 = ld(b2);
+  const double2 e_own = ph.p[own];
+  const double2 e_t = ph.p[isA ? np : nm];  // A: c_A(t+1); B: c_B(t-1)
+  const double2 e0 = ph.p[b0], e1 = ph.p[b1], e2 = ph.p[b2];
+  const double m = g.ms, kap = g.kappa;
+  // signs of the hops: A hop out of slice u carries -1 iff u = 0; B hop iff u = N_t - 1
+  const double sA_t = (t == 0) ? -1.0 : 1.0, sA_tp = (t == g.Nt - 1) ? -1.0 : 1.0;
+  const double sB_t = (t == g.Nt - 1) ? -1.0 : 1.0, sB_tm = (t == 0) ? -1.0 : 1.0;
+  auto cA = [&](double2 e, double sg) { double2 c; c.x = sg * (e.x - m); c.y = sg * e.y; return c; };
+  auto cB = [&](double2 e, double sg) { double2 c; c.x = sg * (e.x - m); c.y = -sg * e.y; return c; };
+  double2 c_own, c_t, k0, k1, k2;
+  if (isA) {
+    c_own = cA(e_own, sA_t);                 // c_A(t)
+    c_t = cA(e_t, sA_tp);                    // c_A(t+1)
+    const double2 d0 = cB(e0, sB_tm), d1 = cB(e1, sB_tm), d2 = cB(e2, sB_tm);  // c_B(t-1)[b]
+    k0.x = c_own.x - d0.x; k0.y = c_own.y + d0.y;   // c_A(t) - conj(c_B)
+    k1.x = c_own.x - d1.x; k1.y = c_own.y + d1.y;
+    k2.x = c_own.x - d2.x; k2.y = c_own.y + d2.y;
+  } else {
+    c_own = cB(e_own, sB_t);                 // c_B(t)
+    c_t = cB(e_t, sB_tm);                    // c_B(t-1)
+    const double2 d0 = cA(e0, sA_tp), d1 = cA(e1, sA_tp), d2 = cA(e2, sA_tp);  // c_A(t+1)[a]
+    k0.x = d0.x - c_own.x; k0.y = -d0.y - c_own.y;  // conj(c_A) - c_B(t)
+    k1.x = d1.x - c_own.x; k1.y = -d1.y - c_own.y;
+    k2.x = d2.x - c_own.x; k2.y = -d2.y - c_own.y;
+  }
+  const double diag = 1.0 + c_own.x * c_own.x + c_own.y * c_own.y + 3.0 * kap * kap + mu2;
+  // temporal: A: - c_A(t) x(t-1) - conj(c_A(t+1)) x(t+1);  B: - c_B(t) x(t+1) - conj(c_B(t-1)) x(t-1)
+  const double2 ta = cmul(c_own, isA ? xm : xp);
+  const double2 tb = cmulc(c_t, isA ? xp : xm);
+  const double2 bo0 = cmul(k0, y0), bo1 = cmul(k1, y1), bo2 = cmul(k2, y2);
+  const double k2s = kap * kap;
+  double2 q;
+  q.x = diag * xs.x - ta.x - tb.x + k2s * (s0.x + s1.x + s2.x + s3.x + s4.x + s5.x) - kap * (bo0.x + bo1.x + bo2.x);
+  q.y = diag * xs.y - ta.y - tb.y + k2s * (s0.y + s1.y + s2.y + s3.y + s4.y + s5.y) - kap * (bo0.y + bo1.y + bo2.y);
+  return q;
+}
+
+// out = [b -] (M M^dagger + mu2) in, FP64 arithmetic (in: FP64 or complex64 slot),
+// partial |out|^2 (mode != RED_NONE).  One pass of the 12-point form.
 template <typename Tin>
-__global__ __launch_bounds__(kBlock) void k_normal2_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in,
-                                                         int s_b, int s_out, int mode) {
+__global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in,
+                                                        int s_b, int s_out, int mode) {
   HUB_PROLOGUE
   (void)sc;
   const Vec<Tin> in(d->vec[s_in]);
   const bool has_b = s_b >= 0;
-  const Vec<double2> bv(has_b ? d->vec[s_b] : nullptr), u(d->vec[S_U]), out(d->vec[s_out]);
-  const PhasePhi<double> phi = phase_of<double>(d);
+  const Vec<double2> bv(has_b ? d->vec[s_b] : nullptr), out(d->vec[s_out]);
+  const PhasePhi<double> ph = phase_of<double>(d);
   const double mu2 = d->mu2;
-  auto ld = [=](int k) { return u[k]; };
-  struct Own {
-    double2 x, b;
-  };
-  auto pre = [=](int n) { return Own{to_c128<Tin>(in[n]), has_b ? bv[n] : cz<double2>()}; };
+  auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
   double acc = 0.0;
-  auto post = [&](int n, double2 q, double2, Own o) {
-    q.x += mu2 * o.x.x;
-    q.y += mu2 * o.x.y;
+#pragma unroll 2
+  for (int m = 0; m < kSitesPerThread; ++m) {
+    const int n = base + m * kBlock;
+    if (n >= g.n) break;
+    double2 q = normal12(g, ph, n, mu2, ld);
     if (has_b) {
-      q.x = o.b.x - q.x;
-      q.y = o.b.y - q.y;
+      const double2 bb = bv[n];
+      q.x = bb.x - q.x;
+      q.y = bb.y - q.y;
     }
     out.set(n, q);
     acc += norm2<double>(q);
-  };
-  stencil_sites<double, false, Spt<double>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+  }
   if (mode == RED_NONE) return;
   const double tot = block_sum(acc);
   store_partials(d, tile, &tot, 1);
 }
+
+
 
 // x = 0, r = b; partial of |b|^2.
 __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restrict__ sys, LaunchList L) {
@@ -1313,14 +1397,6 @@ hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, doub
   return hipGetLastError();
 }
 
-hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
-                          const double2* x, double2* y, int batch, hipStream_t st) {
-  const int nt = (g.n + kPubTile - 1) / kPubTile;
-  Mu2Arr m;
-  for (int b = 0; b < kMaxSys; ++b) m.v[b] = b < batch ? mu2_host[b] : 0.0;
-  hipLaunchKernelGGL(k_normal2_pub, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, m, u, x, y, nt);
-  return hipGetLastError();
-}
 
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi, double scale,
                         int accumulate, double* out, int batch, hipStream_t st, const double2* sub) {
@@ -1360,6 +1436,16 @@ hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
+                          const double2* x, double2* y, int batch, hipStream_t st) {
+  const int nt = (g.n + kPubTile - 1) / kPubTile;
+  Mu2Arr m;
+  for (int b = 0; b < kMaxSys; ++b) m.v[b] = b < batch ? mu2_host[b] : 0.0;
+  hipLaunchKernelGGL(k_normal2_pub, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, m, u, x, y, nt);
+  return hipGetLastError();
+}
+
+
 hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_phase, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, p64, p32, n);
   return hipGetLastError();
@@ -1398,14 +1484,6 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
   return hipGetLastError();
 }
 
-hipError_t launch_mdag_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, hipStream_t st) {
-  const dim3 grid(L.total_tiles), block(kBlock);
-  if (in_c64)
-    hipLaunchKernelGGL(k_mdag_slot<float2>, grid, block, 0, st, sys, L, s_in);
-  else
-    hipLaunchKernelGGL(k_mdag_slot<double2>, grid, block, 0, st, sys, L, s_in);
-  return hipGetLastError();
-}
 
 static hipError_t finish(const SysDesc* sys, const LaunchList& L, int nv, int red_off, RedMode mode,
                          hipStream_t st) {
@@ -1413,13 +1491,14 @@ static hipError_t finish(const SysDesc* sys, const LaunchList& L, int nv, int re
   return hipGetLastError();
 }
 
-hipError_t launch_normal2_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b, int s_out,
-                               RedMode mode, int red_off, hipStream_t st) {
+
+hipError_t launch_normal_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b, int s_out,
+                              RedMode mode, int red_off, hipStream_t st) {
   const dim3 grid(L.total_tiles), block(kBlock);
   if (in_c64)
-    hipLaunchKernelGGL(k_normal2_slot<float2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
+    hipLaunchKernelGGL(k_normal_slot<float2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
   else
-    hipLaunchKernelGGL(k_normal2_slot<double2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
+    hipLaunchKernelGGL(k_normal_slot<double2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == RED_NONE) return e;
   return finish(sys, L, 1, red_off, mode, st);
