@@ -345,13 +345,13 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
   Engine* eng = engine_for(ctx, stream);
   // the phase e^{i phi} once per distinct phi (complex64 too for the mixed solver)
   const bool want32 = o.solver == HUB_FGMRES_MIXED;
-  std::map<const double*, std::pair<double2*, float2*>> phase;
+  std::map<const double*, std::pair<double2*, float*>> phase;
   std::vector<void*> owned;
   hub_status result = HUB_OK;
   for (System& sy : sys) {
     if (phase.count(sy.phi)) continue;
     double2* p64 = (double2*)ctx->pool->alloc((size_t)sy.g.n * 16, stream);
-    float2* p32 = want32 ? (float2*)ctx->pool->alloc((size_t)sy.g.n * 8, stream) : nullptr;
+    float* p32 = want32 ? (float*)ctx->pool->alloc((size_t)sy.g.n * 4, stream) : nullptr;
     if (p64) owned.push_back(p64);
     if (p32) owned.push_back(p32);
     if (!p64 || (want32 && !p32)) {

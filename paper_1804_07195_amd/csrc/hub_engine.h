@@ -59,7 +59,7 @@ struct System {
   double mu2 = 0.0;
   const double* phi = nullptr;
   const double2* ph64 = nullptr;  // (cos phi, sin phi); computed on add if NULL
-  const float2* ph32 = nullptr;   // complex64 phase (mixed solver); computed on add if NULL
+  const float* ph32 = nullptr;    // reduced float phi (mixed solver); computed on add if NULL
   const double2* b = nullptr;
   double2* x = nullptr;
   hub_solve_opts opts{};

@@ -305,7 +305,7 @@ bool Engine::add(System* s) {
   const bool want32 = is_fgmres(s->opts);
   if (ok && (!s->ph64 || (want32 && !s->ph32))) {
     double2* p64 = (double2*)get(n * 16);
-    float2* p32 = want32 ? (float2*)get(n * 8) : nullptr;
+    float* p32 = want32 ? (float*)get(n * 4) : nullptr;
     ok = ok && p64 && (!want32 || p32);
     if (ok && launch_phase(s->phi, p64, p32, (int)n, st_) != hipSuccess) ok = false;
     if (ok) {
@@ -369,6 +369,7 @@ LaunchList Engine::one(System* s) const { return list(std::vector<System*>{s}); 
 LaunchList Engine::list(const std::vector<System*>& v) const {
   LaunchList L;
   std::memset(&L, 0, sizeof(L));
+  L.scal = d_scal_;
   L.nsys = (int)v.size();
   int acc = 0;
   for (int k = 0; k < L.nsys; ++k) {
@@ -675,18 +676,19 @@ hipError_t Engine::finish_block(Block& b) {
     // A system did work in the launch of iteration `it` iff it < its final count
     // (or it is still iterating).
     for (int it = 0; it < b.k; ++it) {
-      double sites = 0.0;
-      for (size_t q = 0; q < b.v.size(); ++q) {
-        const Scal& sc = flags[b.v[q]->slot];
-        if (sc.active || b.its[it][q] < sc.iters) sites += (double)b.v[q]->g.n;
-      }
       for (int stage = 0; stage < 2; ++stage) {
+        double bytes = 0.0;
+        for (size_t q = 0; q < b.v.size(); ++q) {
+          const Scal& sc = flags[b.v[q]->slot];
+          const int its = b.its[it][q];
+          if (sc.active || its < sc.iters) bytes += (double)b.v[q]->g.n * cg_bytes(single, stage + 1, its);
+        }
         float ms = 0.0f;
         HUB_TRY(hipEventElapsedTime(&ms, b.kev[4 * it + 2 * stage], b.kev[4 * it + 2 * stage + 1]));
         KernelStat& ks = stat[single ? 1 : 0][stage];
         ks.launches++;
         ks.ms += ms;
-        ks.bytes += sites * kCgBytes[single ? 1 : 0][stage];
+        ks.bytes += bytes;
       }
     }
   }

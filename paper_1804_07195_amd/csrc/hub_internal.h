@@ -59,12 +59,13 @@ struct Geom {
 // decision whichever value they see).
 struct Scal {
   double rrv[2];  // |r_k|^2 of CG iteration k in rrv[k & 1]
+  double alpha[2];  // alpha_k of CG iteration k in alpha[k & 1]
   double stop2;   // CG stops once |r|^2 <= stop2
   double red[kMaxRed];               // results of the last generic reduction
   double y[2 * kMaxRestart];         // FGMRES update coefficients (host-written)
   int iters;      // CG iterations performed when the CG stopped
   int maxit;
-  int active;     // 1 while CG iterations continue
+  int active;     // CG: 1 iterating, 2 stopped by the last stage 1 (the next stage 2 sets 0), 0 stopped
   int pad;
 };
 
@@ -74,7 +75,7 @@ struct SysDesc {
   double mu2;
   const double* phi;     // float64 phi [n]
   const double2* ph64;   // (cos phi, sin phi) [n], FP64 solver kernels
-  const float2* ph32;    // the same in complex64 [n] (single-precision path)
+  const float* ph32;     // phi reduced to [-pi, pi] and rounded to float [n] (single-precision path)
   Scal* sc;
   double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
   double* part1;         // per-tile partials of CG stage 1 [ntiles]
@@ -123,6 +124,7 @@ struct MsDesc {
 
 // Systems of one batched launch: workgroup tiles are laid out system after system.
 struct LaunchList {
+  Scal* scal;           // the engine's Scal array: system slot k uses scal[k]
   int nsys;
   int total_tiles;
   int tile_begin[kMaxSys + 1];
@@ -168,8 +170,9 @@ hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, co
                         const double2* sub = nullptr);
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
                          double* result, hipStream_t st);
-// p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, rounded to complex64.
-hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st);
+// p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, phi reduced to [-pi, pi]
+// and rounded to float (the complex64 kernels evaluate the phase from it).
+hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st);
 // y_b = M u_b + mu2_b x_b (the second pass of the public normal operator, u = M^dagger x).
 hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
                           const double2* x, double2* y, int batch, hipStream_t st);
@@ -190,8 +193,13 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
 hipError_t launch_ms_start(const MsDesc* d, int ntiles, hipStream_t st);
 hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st);
 // Algorithmic bytes per site of each CG stage (reads + writes of distinct vectors).
-// The phase e^{i phi} is read precomputed: 16 bytes per site in FP64, 8 in complex64.
-constexpr double kCgBytes[2][2] = {{80.0, 112.0}, {40.0, 56.0}};  // [single][stage-1]
+// FP64 reads the phase e^{i phi} precomputed (16 bytes per site); complex64 reads the
+// reduced angle as a float (4 bytes) and evaluates cos and sin in registers.  Stage 2
+// updates the solution at odd iterations only (x and p_{it-1} read, x written).
+constexpr double kCgBytes[2][3] = {{80.0, 80.0, 128.0}, {36.0, 36.0, 60.0}};  // [single][stage 1, 2 even, 2 odd]
+inline double cg_bytes(bool single, int stage, int it) {
+  return kCgBytes[single ? 1 : 0][stage == 1 ? 0 : 1 + (it & 1)];
+}
 // Every reduction below leaves per-tile partials; a finalisation kernel (one
 // workgroup per system) sums them in a fixed order into sc->red[red_off..] and,
 // with RED_CG_SETUP, starts a CG on the result (pa, pr, pi of the launch list).

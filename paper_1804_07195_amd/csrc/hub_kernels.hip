@@ -19,6 +19,8 @@
 //   only on its own shape, never on the other systems of the launch.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "hub_internal.h"
 
 namespace hub {
@@ -134,11 +136,38 @@ template <typename T> struct Real {
   __device__ __forceinline__ hub_f2v pair(int k) const { return ((HUB_GAS hub_f2v*)p)[k >> 1]; }
 };
 
-// The phase e^{i phi} a stencil needs, from one of two sources:
+// cos x and sin x in FP32 for the complex64 solver kernels, |x| <= pi in practice (the
+// angle is reduced when the solve starts): r = x - q pi/2 with q the integer nearest
+// 2x/pi (difference and product in FP64, exact far below FP32 rounding), cos r and
+// sin r on |r| <= pi/4 from their Taylor series through degree 10 and 9 (the first
+// omitted terms are below 2.5e-9, under half an FP32 ulp), then (cos r, sin r) turned
+// by q quarter turns.  Error against e^{ix}: about one FP32 ulp.
+__device__ __forceinline__ void cis32(float x, float& c, float& s) {
+  const float q = rintf(x * 0.636619772f);
+  const float r = (float)fma(-(double)q, 1.5707963267948966, (double)x);
+  const float r2 = r * r;
+  float ps = fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);  // 1/9!, -1/7!
+  ps = fmaf(ps, r2, 8.33333333e-3f);                      // 1/5!
+  ps = fmaf(ps, r2, -1.66666667e-1f);                     // -1/3!
+  const float sr = fmaf(ps * r2, r, r);
+  float pc = fmaf(r2, -2.75573192e-7f, 2.48015873e-5f);  // -1/10!, 1/8!
+  pc = fmaf(pc, r2, -1.38888889e-3f);                     // -1/6!
+  pc = fmaf(pc, r2, 4.16666667e-2f);                      // 1/4!
+  pc = fmaf(pc, r2, -0.5f);
+  const float cr = fmaf(pc, r2, 1.0f);
+  const int k = (int)q & 3;
+  c = (k == 0) ? cr : (k == 1) ? -sr : (k == 2) ? -cr : sr;
+  s = (k == 0) ? sr : (k == 1) ? cr : (k == 2) ? -sr : -cr;
+}
+
+// The phase e^{i phi} a stencil needs, from one of three sources:
 //  * AnglePhi - phi itself; cos and sin are computed per site (the public operator
 //               kernels, whose input is phi);
-//  * PhasePhi - (cos phi, sin phi) precomputed once per solve (the solver kernels:
-//               a 16- or 8-byte load replaces a sincos per site).
+//  * PhasePhi - (cos phi, sin phi) precomputed once per solve (the FP64 solver
+//               kernels: a 16-byte load replaces a sincos per site);
+//  * Angle32  - phi reduced to [-pi, pi] and rounded to float once per solve, cos and
+//               sin from cis32 (the complex64 solver kernels: a 4-byte load and a few
+//               FMAs, against 8 bytes for a precomputed complex64 phase).
 // load(k) returns the raw value of site k, cs() turns it into (cos, sin); load2 / cs2
 // do the same for the two sites k, k+1 (k even) of the complex64 pair path.
 template <typename R> struct AnglePhi {
@@ -150,6 +179,16 @@ template <typename R> struct AnglePhi {
   __device__ __forceinline__ void cs(Raw v, R& c, R& s) const { phase_cs(v, c, s); }
   __device__ __forceinline__ Raw2 load2(int k) const { return a.pair(k); }
   __device__ __forceinline__ void cs2(Raw2 v, int h, float& c, float& s) const { phase_cs(h ? v.y : v.x, c, s); }
+};
+struct Angle32 {
+  Real<float> a;
+  using Raw = float;
+  using Raw2 = hub_f2v;
+  __device__ __forceinline__ explicit Angle32(const void* q) : a(q) {}
+  __device__ __forceinline__ Raw load(int k) const { return a[k]; }
+  __device__ __forceinline__ void cs(Raw v, float& c, float& s) const { cis32(v, c, s); }
+  __device__ __forceinline__ Raw2 load2(int k) const { return a.pair(k); }
+  __device__ __forceinline__ void cs2(Raw2 v, int h, float& c, float& s) const { cis32(h ? v.y : v.x, c, s); }
 };
 template <typename R> struct PhasePhi {
   using C = typename V2<R>::T;
@@ -466,13 +505,15 @@ __device__ __forceinline__ int find_sys(const LaunchList& L, int lt) {
   return lo;
 }
 
-template <typename R> __device__ __forceinline__ PhasePhi<R> phase_of(const SysDesc* d);
+// The phase source of the solver kernels in precision R.
+template <typename R> struct SolverPhase;
+template <> struct SolverPhase<double> { using T = PhasePhi<double>; };
+template <> struct SolverPhase<float> { using T = Angle32; };
+template <typename R> __device__ __forceinline__ typename SolverPhase<R>::T phase_of(const SysDesc* d);
 template <> __device__ __forceinline__ PhasePhi<double> phase_of<double>(const SysDesc* d) {
   return PhasePhi<double>(d->ph64);
 }
-template <> __device__ __forceinline__ PhasePhi<float> phase_of<float>(const SysDesc* d) {
-  return PhasePhi<float>(d->ph32);
-}
+template <> __device__ __forceinline__ Angle32 phase_of<float>(const SysDesc* d) { return Angle32(d->ph32); }
 
 __device__ __forceinline__ int load_active(Scal* sc) {
   return __hip_atomic_load(&sc->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -605,23 +646,20 @@ __global__ __launch_bounds__(kBlock) void k_dot_finish(const double* __restrict_
   if (threadIdx.x == 0) result[blockIdx.x] = s;
 }
 
-// (cos phi, sin phi) per site in FP64, and rounded to complex64 when p32 is given.
+// (cos phi, sin phi) per site in FP64 and, when p32 is given, phi - 2 pi k (k the
+// integer nearest phi / 2 pi, in FP64) rounded to float.
 __global__ __launch_bounds__(kBlock) void k_phase(const double* __restrict__ phi, double2* __restrict__ p64,
-                                                  float2* __restrict__ p32, int n) {
+                                                  float* __restrict__ p32, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
+  const double a = phi[i];
   double c, s;
-  sincos(phi[i], &s, &c);
+  sincos(a, &s, &c);
   double2 v;
   v.x = c;
   v.y = s;
   p64[i] = v;
-  if (p32) {
-    float2 w;
-    w.x = (float)c;
-    w.y = (float)s;
-    p32[i] = w;
-  }
+  if (p32) p32[i] = (float)fma(-rint(a * 0.15915494309189535), 6.283185307179586, a);
 }
 
 // Molecular dynamics (Sec. 5.2): phi += eps pi (T_pi), and the momentum kick
@@ -647,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
   const int kk = find_sys(L, lt);                      \
   const SysDesc* __restrict__ d = sys + L.sys[kk];     \
   const int tile = lt - L.tile_begin[kk];              \
-  Scal* sc = d->sc;                                    \
+  Scal* sc = L.scal + L.sys[kk];                       \
   const Geom g = d->g;                                 \
   const int base = tile * kTile + threadIdx.x;
 
@@ -656,6 +694,10 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
 //   test; p_new = r + beta p_old with beta = |r_it|^2 / |r_{it-1}|^2 (p_new = r at
 //   it = 0), u = M^dagger p_new, partial of |u|^2 + mu^2 |p_new|^2 = <p, A p>.
 // The loads of r and p_old are issued before the partial sums are read.
+// The solution advances every second iteration (see k_cg2): a stage 1 that stops at
+// an odd it adds the pending alpha_{it-1} p_{it-1} (p_old here) to x.  It marks the
+// stop with active = 2 rather than 0 so that every workgroup of this launch still
+// takes the stopping path; the next stage 2 sets 0.
 template <typename C>
 struct RP {
   C r, p;
@@ -670,7 +712,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
   const int it = L.it[kk];
   const R mu2 = (R)d->mu2;
   const Vec<C> r(d->vec[sR]), po(d->vec[sP + (it & 1)]), pn(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]);
-  const PhasePhi<R> phi = phase_of<R>(d);
+  const auto phi = phase_of<R>(d);
   R beta = 0;
   bool stopped = false;  // same value in every thread of every workgroup of the system
   // |r_it|^2, the stopping test and beta, once the stencil loads are in flight
@@ -683,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
       if (first) {
         sc->rrv[it & 1] = rr;
         sc->iters = it;
-        store_active(sc, 0);
+        store_active(sc, 2);
       }
       stopped = true;
       return false;
@@ -750,83 +792,128 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
     }
   }
   // a system that met its stopping test in `mid` writes no partial (none is read)
-  if (stopped) return;
+  if (stopped) {
+    if (it & 1) {
+      const R a = (R)sc->alpha[(it - 1) & 1];
+      const Vec<C> x(d->vec[L.pi[kk]]);
+      const int end = min((tile + 1) * kTile, g.n);
+      for (int k = tile * kTile + (int)threadIdx.x; k < end; k += kBlock) {
+        const C pv = po[k];
+        C xv = x[k];
+        xv.x = fma(a, pv.x, xv.x);
+        xv.y = fma(a, pv.y, xv.y);
+        x.set(k, xv);
+      }
+    }
+    return;
+  }
   const double tot = (double)block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part1).set(tile, tot);
 }
 
 // CG stage 2 of iteration it: alpha = |r_it|^2 / <p, A p> (stage-1 partials),
-// q = M u + mu^2 p, x += alpha p, r -= alpha q, partial of |r_{it+1}|^2.
-// The solution slot of system k is L.pi[k].  Loads are issued before alpha is read.
+// q = M u + mu^2 p, r -= alpha q, partial of |r_{it+1}|^2, and the solution every
+// second iteration: x += alpha_{it-1} p_{it-1} + alpha_it p_it at odd it (p_{it-1}
+// is still in the other slot of the pair), which saves a read and a write of x per
+// two iterations for one read of p_{it-1}.  The solution slot of system k is L.pi[k].
+// Loads are issued before alpha is read.  A system whose stage 1 stopped (active 2)
+// does nothing here; workgroup 0 marks it stopped for good.
+template <typename C, bool UPD>
+struct Own {
+  C p, r, x, q;  // x, q (p_{it-1}) loaded only when UPD
+};
 template <typename R, typename PhiT>
 __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
                                                 int sU) {
   using C = typename V2<R>::T;
   HUB_PROLOGUE
-  if (!load_active(sc)) return;
+  const int act = load_active(sc);
+  if (act != 1) {
+    if (act == 2 && tile == 0 && threadIdx.x == 0) store_active(sc, 0);
+    return;
+  }
   const int it = L.it[kk];
-  R alpha = 0;
+  R alpha = 0, alpha_prev = 0;
   auto mid = [&]() -> bool {
     const double pq = sum_partials(d->part1, d->ntiles, 1);
-    alpha = (R)(sc->rrv[it & 1] / pq);
+    const double a = sc->rrv[it & 1] / pq;
+    if (tile == 0 && threadIdx.x == 0) sc->alpha[it & 1] = a;
+    alpha = (R)a;
+    if (it & 1) alpha_prev = (R)sc->alpha[(it - 1) & 1];
     return true;
   };
   const R mu2 = (R)d->mu2;
-  const Vec<C> p(d->vec[sP + 1 - (it & 1)]), u(d->vec[sU]), x(d->vec[L.pi[kk]]), r(d->vec[sR]);
-  const PhasePhi<R> phi = phase_of<R>(d);
-  struct Own {
-    C p, x, r;
-  };
+  const Vec<C> p(d->vec[sP + 1 - (it & 1)]), pp(d->vec[sP + (it & 1)]), u(d->vec[sU]), x(d->vec[L.pi[kk]]),
+      r(d->vec[sR]);
+  const auto phi = phase_of<R>(d);
   R acc = 0;
-  bool done = false;
-  if constexpr (sizeof(R) == 4) {
-    if ((g.L2 & 1) == 0) {
-      struct Own2 {
-        C64x2 p, x, r;
-      };
-      auto ld2 = [=](int k) { return u.pair(k); };
-      auto ld1 = [=](int k) { return u[k]; };
-      auto pre2 = [=](int n) { return Own2{p.pair(n), x.pair(n), r.pair(n)}; };
-      auto post2 = [&](int n, C64x2 q, C64x2, Own2 o) {
-        C64x2 xv, rv;
-        C qa = q.a, qb = q.b;
-        qa.x += mu2 * o.p.a.x;
-        qa.y += mu2 * o.p.a.y;
-        qb.x += mu2 * o.p.b.x;
-        qb.y += mu2 * o.p.b.y;
-        xv.a.x = o.x.a.x + alpha * o.p.a.x;
-        xv.a.y = o.x.a.y + alpha * o.p.a.y;
-        xv.b.x = o.x.b.x + alpha * o.p.b.x;
-        xv.b.y = o.x.b.y + alpha * o.p.b.y;
-        rv.a.x = o.r.a.x - alpha * qa.x;
-        rv.a.y = o.r.a.y - alpha * qa.y;
-        rv.b.x = o.r.b.x - alpha * qb.x;
-        rv.b.y = o.r.b.y - alpha * qb.y;
-        x.set_pair(n, xv);
-        r.set_pair(n, rv);
-        acc += norm2<R>(rv.a) + norm2<R>(rv.b);
-      };
-      stencil_pairs<false>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
-      done = true;
+  auto run = [&](auto upd) {
+    constexpr bool U = decltype(upd)::value;
+    if constexpr (sizeof(R) == 4) {
+      if ((g.L2 & 1) == 0) {
+        auto ld2 = [=](int k) { return u.pair(k); };
+        auto ld1 = [=](int k) { return u[k]; };
+        auto pre2 = [=](int n) {
+          Own<C64x2, U> o;
+          o.p = p.pair(n);
+          o.r = r.pair(n);
+          if constexpr (U) {
+            o.x = x.pair(n);
+            o.q = pp.pair(n);
+          }
+          return o;
+        };
+        auto post2 = [&](int n, C64x2 q, C64x2, Own<C64x2, U> o) {
+          C64x2 rv;
+          rv.a.x = o.r.a.x - alpha * fma(mu2, o.p.a.x, q.a.x);
+          rv.a.y = o.r.a.y - alpha * fma(mu2, o.p.a.y, q.a.y);
+          rv.b.x = o.r.b.x - alpha * fma(mu2, o.p.b.x, q.b.x);
+          rv.b.y = o.r.b.y - alpha * fma(mu2, o.p.b.y, q.b.y);
+          r.set_pair(n, rv);
+          if constexpr (U) {
+            C64x2 xv;
+            xv.a.x = fma(alpha, o.p.a.x, fma(alpha_prev, o.q.a.x, o.x.a.x));
+            xv.a.y = fma(alpha, o.p.a.y, fma(alpha_prev, o.q.a.y, o.x.a.y));
+            xv.b.x = fma(alpha, o.p.b.x, fma(alpha_prev, o.q.b.x, o.x.b.x));
+            xv.b.y = fma(alpha, o.p.b.y, fma(alpha_prev, o.q.b.y, o.x.b.y));
+            x.set_pair(n, xv);
+          }
+          acc += norm2<R>(rv.a) + norm2<R>(rv.b);
+        };
+        stencil_pairs<false>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
+        return;
+      }
     }
-  }
-  if (!done) {
     auto ld = [=](int k) { return u[k]; };
-    auto pre = [=](int n) { return Own{p[n], x[n], r[n]}; };
-    auto post = [&](int n, C q, C, Own o) {
-      q.x += mu2 * o.p.x;
-      q.y += mu2 * o.p.y;
-      C xv = o.x, rv = o.r;
-      xv.x += alpha * o.p.x;
-      xv.y += alpha * o.p.y;
-      rv.x -= alpha * q.x;
-      rv.y -= alpha * q.y;
-      x.set(n, xv);
+    auto pre = [=](int n) {
+      Own<C, U> o;
+      o.p = p[n];
+      o.r = r[n];
+      if constexpr (U) {
+        o.x = x[n];
+        o.q = pp[n];
+      }
+      return o;
+    };
+    auto post = [&](int n, C q, C, Own<C, U> o) {
+      C rv;
+      rv.x = o.r.x - alpha * fma(mu2, o.p.x, q.x);
+      rv.y = o.r.y - alpha * fma(mu2, o.p.y, q.y);
       r.set(n, rv);
+      if constexpr (U) {
+        C xv;
+        xv.x = fma(alpha, o.p.x, fma(alpha_prev, o.q.x, o.x.x));
+        xv.y = fma(alpha, o.p.y, fma(alpha_prev, o.q.y, o.x.y));
+        x.set(n, xv);
+      }
       acc += norm2<R>(rv);
     };
     stencil_sites<R, false, Spt<R>::v>(g, phi, base, ld, Same{}, pre, mid, post);
-  }
+  };
+  if (it & 1)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
   const double tot = (double)block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }
@@ -1446,7 +1533,7 @@ hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_hos
 }
 
 
-hipError_t launch_phase(const double* phi, double2* p64, float2* p32, int n, hipStream_t st) {
+hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_phase, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, p64, p32, n);
   return hipGetLastError();
 }
