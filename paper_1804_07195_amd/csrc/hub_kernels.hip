@@ -48,7 +48,43 @@ template <typename R> struct V2;
 template <> struct V2<double> { using T = double2; };
 template <> struct V2<float> { using T = float2; };
 
-__device__ __forceinline__ void phase_cs(double ph, double& c, double& s) { sincos(ph, &s, &c); }
+// cos x and sin x in FP64 for the public operator kernels (the phase of each site from
+// phi): Cody-Waite reduction r = x - q pi/2 with q the integer nearest 2x/pi and pi/2
+// split into the nearest double and its remainder (each product inside one FMA, so r is
+// exact to an ulp for |q| < 2^20), then the Taylor series of cos r and sin r through
+// degree 18 and 17 on |r| <= pi/4 (first omitted terms below 5e-17) and a turn by q
+// quarter turns.  Error against e^{ix}: under 2e-16, without the library routine's
+// branch for huge arguments.
+__device__ __forceinline__ void cis64(double x, double& c, double& s) {
+  const double q = rint(x * 0.6366197723675814);
+  double r = fma(-q, 1.5707963267948966, x);
+  r = fma(-q, 6.123233995736766e-17, r);
+  const double r2 = r * r;
+  double ps = 2.8114572543455206e-15;         // 1/17!
+  ps = fma(ps, r2, -7.647163731819816e-13);   // -1/15!
+  ps = fma(ps, r2, 1.6059043836821613e-10);   // 1/13!
+  ps = fma(ps, r2, -2.505210838544172e-08);   // -1/11!
+  ps = fma(ps, r2, 2.7557319223985893e-06);   // 1/9!
+  ps = fma(ps, r2, -0.0001984126984126984);   // -1/7!
+  ps = fma(ps, r2, 0.008333333333333333);     // 1/5!
+  ps = fma(ps, r2, -0.16666666666666666);     // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  double pc = 1.5619206968586225e-16;         // 1/18!
+  pc = fma(pc, r2, -4.779477332387385e-14);   // -1/16!
+  pc = fma(pc, r2, 1.1470745597729725e-11);   // 1/14!
+  pc = fma(pc, r2, -2.08767569878681e-09);    // -1/12!
+  pc = fma(pc, r2, 2.755731922398589e-07);    // 1/10!
+  pc = fma(pc, r2, -2.48015873015873e-05);    // -1/8!
+  pc = fma(pc, r2, 0.001388888888888889);     // 1/6!
+  pc = fma(pc, r2, -0.041666666666666664);    // -1/4!
+  pc = fma(pc, r2, 0.5);                      // 1/2!
+  const double cr = fma(-pc, r2, 1.0);
+  const int k = (int)q & 3;
+  c = (k == 0) ? cr : (k == 1) ? -sr : (k == 2) ? -cr : sr;
+  s = (k == 0) ? sr : (k == 1) ? cr : (k == 2) ? -sr : -cr;
+}
+
+__device__ __forceinline__ void phase_cs(double ph, double& c, double& s) { cis64(ph, c, s); }
 __device__ __forceinline__ void phase_cs(float ph, float& c, float& s) { sincosf(ph, &s, &c); }
 
 // Workgroups are dispatched round-robin over the XCDs; give XCD x the x-th
@@ -600,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restri
         sgn = wrap ? -1.0 : 1.0;
       }
       double c, s;
-      sincos(phi[n], &s, &c);
+      cis64(phi[n], c, s);
       if (!isA) s = -s;
       const double2 e = eta[off + n];
       double2 z = xi[off + tn];
