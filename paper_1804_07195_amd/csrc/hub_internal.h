@@ -136,6 +136,21 @@ struct LaunchList {
   int it[kMaxSys];      // CG iteration index of each system in this launch
 };
 
+// The part of a launch list the CG kernels read, for up to N systems.  It is the
+// kernel argument of every CG launch, so it is kept small: N = 4 covers most launches
+// (a 2.3 KB argument costs ~0.2 us per launch on the device and more on the host).
+template <int N>
+struct CgList {
+  Scal* scal;
+  int nsys;
+  int total_tiles;
+  int tile_begin[N + 1];
+  int sys[N];
+  int pi[N];   // solution slot
+  int it[N];   // CG iteration index
+};
+constexpr int kSmallCg = 4;
+
 // Vector slot roles.  FP64 slots hold double2 [n]; C64 slots hold float2 [n].
 enum Slot : int {
   S_B = 0,     // right-hand side (FP64)

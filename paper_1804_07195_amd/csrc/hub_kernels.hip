@@ -19,6 +19,7 @@
 //   only on its own shape, never on the other systems of the launch.
 #include <hip/hip_ext.h>
 
+#include <cstring>
 #include <type_traits>
 
 #include "hub_internal.h"
@@ -532,7 +533,8 @@ __device__ __forceinline__ double sum_partials(const double* part, int cnt, int 
   return block_sum(acc);
 }
 
-__device__ __forceinline__ int find_sys(const LaunchList& L, int lt) {
+template <typename LL>
+__device__ __forceinline__ int find_sys(const LL& L, int lt) {
   int lo = 0, hi = L.nsys - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -739,9 +741,8 @@ struct RP {
   C r, p;
 };
 
-template <typename R, typename PhiT>
-__global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
-                                                int sU) {
+template <typename R, typename LL>
+__global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys, LL L, int sR, int sP, int sU) {
   using C = typename V2<R>::T;
   HUB_PROLOGUE
   if (!load_active(sc)) return;
@@ -858,9 +859,8 @@ template <typename C, bool UPD>
 struct Own {
   C p, r, x, q;  // x, q (p_{it-1}) loaded only when UPD
 };
-template <typename R, typename PhiT>
-__global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LaunchList L, int sR, int sP,
-                                                int sU) {
+template <typename R, typename LL>
+__global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LL L, int sR, int sP, int sU) {
   using C = typename V2<R>::T;
   HUB_PROLOGUE
   const int act = load_active(sc);
@@ -1574,36 +1574,61 @@ hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipS
   return hipGetLastError();
 }
 
+template <int N>
+static CgList<N> cg_list(const LaunchList& L) {
+  CgList<N> c;
+  std::memset(&c, 0, sizeof(c));
+  c.scal = L.scal;
+  c.nsys = L.nsys;
+  c.total_tiles = L.total_tiles;
+  for (int k = 0; k <= N; ++k) c.tile_begin[k] = k <= L.nsys ? L.tile_begin[k] : L.total_tiles;
+  for (int k = 0; k < L.nsys; ++k) {
+    c.sys[k] = L.sys[k];
+    c.pi[k] = L.pi[k];
+    c.it[k] = L.it[k];
+  }
+  return c;
+}
+
+// One CG stage (1 or 2) over the list; with events, the launch records its own start and end.
+template <typename R, typename LL>
+static void cg_stage(const SysDesc* sys, const LL& c, int stage, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(c.total_tiles), block(kBlock);
+  const bool single = sizeof(R) == 4;
+  const int sR = single ? (int)S_R32 : (int)S_R, sP = single ? (int)S_P32 : (int)S_P0,
+            sU = single ? (int)S_U32 : (int)S_U;
+  if (e0)
+    hipExtLaunchKernelGGL((stage == 1 ? k_cg1<R, LL> : k_cg2<R, LL>), grid, block, 0, st, e0, e1, 0, sys, c, sR, sP,
+                          sU);
+  else
+    hipLaunchKernelGGL((stage == 1 ? k_cg1<R, LL> : k_cg2<R, LL>), grid, block, 0, st, sys, c, sR, sP, sU);
+}
+
+template <typename R>
+static void cg_stage_any(const SysDesc* sys, const LaunchList& L, int stage, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
+  if (L.nsys <= kSmallCg)
+    cg_stage<R>(sys, cg_list<kSmallCg>(L), stage, st, e0, e1);
+  else
+    cg_stage<R>(sys, cg_list<kMaxSys>(L), stage, st, e0, e1);
+}
+
 hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st) {
-  const dim3 grid(L.total_tiles), block(kBlock);
-  if (single) {
-    hipLaunchKernelGGL((k_cg1<float, float>), grid, block, 0, st, sys, L, (int)S_R32, (int)S_P32, (int)S_U32);
-    hipLaunchKernelGGL((k_cg2<float, float>), grid, block, 0, st, sys, L, (int)S_R32, (int)S_P32, (int)S_U32);
-  } else {
-    hipLaunchKernelGGL((k_cg1<double, double>), grid, block, 0, st, sys, L, (int)S_R, (int)S_P0, (int)S_U);
-    hipLaunchKernelGGL((k_cg2<double, double>), grid, block, 0, st, sys, L, (int)S_R, (int)S_P0, (int)S_U);
+  for (int stage = 1; stage <= 2; ++stage) {
+    if (single)
+      cg_stage_any<float>(sys, L, stage, st, nullptr, nullptr);
+    else
+      cg_stage_any<double>(sys, L, stage, st, nullptr, nullptr);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
                            hipEvent_t e0, hipEvent_t e1) {
-  const dim3 grid(L.total_tiles), block(kBlock);
-  if (single) {
-    if (stage == 1)
-      hipExtLaunchKernelGGL((k_cg1<float, float>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R32, (int)S_P32,
-                            (int)S_U32);
-    else
-      hipExtLaunchKernelGGL((k_cg2<float, float>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R32, (int)S_P32,
-                            (int)S_U32);
-  } else {
-    if (stage == 1)
-      hipExtLaunchKernelGGL((k_cg1<double, double>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R, (int)S_P0,
-                            (int)S_U);
-    else
-      hipExtLaunchKernelGGL((k_cg2<double, double>), grid, block, 0, st, e0, e1, 0, sys, L, (int)S_R, (int)S_P0,
-                            (int)S_U);
-  }
+  if (single)
+    cg_stage_any<float>(sys, L, stage, st, e0, e1);
+  else
+    cg_stage_any<double>(sys, L, stage, st, e0, e1);
   return hipGetLastError();
 }
 
