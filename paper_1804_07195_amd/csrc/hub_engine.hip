@@ -236,9 +236,11 @@ static bool is_fgmres(const hub_solve_opts& o) { return o.solver == HUB_FGMRES_M
 size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
   const size_t n = (size_t)g.n;
   const size_t part = Pool::rounded((size_t)ntiles_of(g.n) * (kMaxRed + 2) * sizeof(double));
-  if (!is_fgmres(o)) return 4 * Pool::rounded(n * 16) + part;
+  // vectors + the phase tables that `add` computes when the caller brings none
+  // (FP64 phase n * 16; the mixed solver's float angle n * 4)
+  if (!is_fgmres(o)) return 5 * Pool::rounded(n * 16) + part;
   const int m = o.restart_m;
-  return (size_t)(m + 3) * Pool::rounded(n * 16) + (size_t)(m + 4) * Pool::rounded(n * 8) +
+  return (size_t)(m + 4) * Pool::rounded(n * 16) + (size_t)(m + 4) * Pool::rounded(n * 8) +
          Pool::rounded(n * 4) + part;
 }
 
