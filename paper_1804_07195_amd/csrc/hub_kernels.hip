@@ -19,6 +19,7 @@
 //   only on its own shape, never on the other systems of the launch.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -563,10 +564,16 @@ __device__ __forceinline__ void store_active(Scal* sc, int v) {
 // ---------------------------------------------------------------------------
 // Public operator kernels (shared phi, batch of vectors, no descriptors).  They
 // have no reduction partials, so they use smaller tiles (two sites per thread,
-// both loaded together): more waves in flight than the CG kernels' tiles.
+// both loaded together): more waves in flight than the CG kernels' tiles.  A
+// workgroup applies the operator to a group of `per` consecutive vectors of the
+// batch: the site indices, phi and its phase are loaded and evaluated once per site
+// for the whole group (the launcher makes the group the whole batch whenever the
+// lattice alone gives enough workgroups).
 // ---------------------------------------------------------------------------
 constexpr int kPubSites = 2;
 constexpr int kPubTile = kBlock * kPubSites;
+
+// One vector per workgroup: all loads of a round in flight together, then the phase.
 template <bool DAG>
 __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restrict__ phi,
                                                   const double2* __restrict__ x, double2* __restrict__ y,
@@ -582,9 +589,55 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   stencil_sites<double, DAG, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{}, post);
 }
 
+// A group of `per` vectors per workgroup (separate kernel, so that the one-vector
+// kernel keeps its register budget).
+template <bool DAG>
+__global__ __launch_bounds__(kBlock) void k_apply_grp(Geom g, const double* __restrict__ phi,
+                                                      const double2* __restrict__ x, double2* __restrict__ y,
+                                                      int ntiles, int per, int batch) {
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int grp = l / ntiles, tile = l - grp * ntiles;
+  const int b0 = grp * per, b1 = min(batch, b0 + per);
+  const int base = tile * kPubTile + threadIdx.x;
+  SiteIdx st[kPubSites];
+  bool ok[kPubSites];
+  double ph[kPubSites], c[kPubSites], s[kPubSites];
+#pragma unroll
+  for (int m = 0; m < kPubSites; ++m) {
+    int n = base + m * kBlock;
+    ok[m] = n < g.n;
+    n = ok[m] ? n : g.n - 1;
+    st[m] = site_index<DAG>(g, n);
+    ph[m] = phi[st[m].pn];
+  }
+  for (int b = b0; b < b1; ++b) {
+    const double2* __restrict__ xb = x + (size_t)b * g.n;
+    double2* __restrict__ yb = y + (size_t)b * g.n;
+    double2 xs[kPubSites], xt[kPubSites], x0[kPubSites], x1[kPubSites], x2[kPubSites];
+#pragma unroll
+    for (int m = 0; m < kPubSites; ++m) {
+      xs[m] = xb[st[m].n];
+      xt[m] = xb[st[m].tn];
+      x0[m] = xb[st[m].h0];
+      x1[m] = xb[st[m].h1];
+      x2[m] = xb[st[m].h2];
+    }
+    if (b == b0) {
+#pragma unroll
+      for (int m = 0; m < kPubSites; ++m) cis64(ph[m], c[m], s[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < kPubSites; ++m) {
+      const double2 v = stencil_combine<double, DAG>(g, st[m], c[m], s[m], xs[m], xt[m], x0[m], x1[m], x2[m]);
+      if (ok[m]) yb[st[m].n] = v;
+    }
+  }
+}
+
 struct Mu2Arr { double v[kMaxSys]; };
 
-// y_b = M u_b + mu2_b x_b: the second pass of the public normal operator (u = M^dagger x).
+// y_b = M u_b + mu2_b x_b: the second pass of the public normal operator (u = M^dagger x),
+// one vector per workgroup.
 __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __restrict__ phi, Mu2Arr mu2,
                                                         const double2* __restrict__ u,
                                                         const double2* __restrict__ x, double2* __restrict__ y,
@@ -603,6 +656,62 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
   };
   stencil_sites<double, false, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{},
                                                      post);
+}
+
+// The same for a group of `per` vectors per workgroup.
+__global__ __launch_bounds__(kBlock) void k_normal2_grp(Geom g, const double* __restrict__ phi, Mu2Arr mu2,
+                                                        const double2* __restrict__ u,
+                                                        const double2* __restrict__ x, double2* __restrict__ y,
+                                                        int ntiles, int per, int batch) {
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int grp = l / ntiles, tile = l - grp * ntiles;
+  const int b0 = grp * per, b1 = min(batch, b0 + per);
+  const int base = tile * kPubTile + threadIdx.x;
+  SiteIdx st[kPubSites];
+  bool ok[kPubSites];
+  double ph[kPubSites], c[kPubSites], s[kPubSites];
+#pragma unroll
+  for (int m = 0; m < kPubSites; ++m) {
+    int n = base + m * kBlock;
+    ok[m] = n < g.n;
+    n = ok[m] ? n : g.n - 1;
+    st[m] = site_index<false>(g, n);
+    ph[m] = phi[st[m].pn];
+  }
+  for (int b = b0; b < b1; ++b) {
+    const size_t off = (size_t)b * g.n;
+    const double m2 = mu2.v[b];
+    double2 us[kPubSites], ut[kPubSites], u0[kPubSites], u1[kPubSites], u2[kPubSites], xv[kPubSites];
+#pragma unroll
+    for (int m = 0; m < kPubSites; ++m) {
+      us[m] = u[off + st[m].n];
+      ut[m] = u[off + st[m].tn];
+      u0[m] = u[off + st[m].h0];
+      u1[m] = u[off + st[m].h1];
+      u2[m] = u[off + st[m].h2];
+      xv[m] = x[off + st[m].n];
+    }
+    if (b == b0) {
+#pragma unroll
+      for (int m = 0; m < kPubSites; ++m) cis64(ph[m], c[m], s[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < kPubSites; ++m) {
+      double2 q = stencil_combine<double, false>(g, st[m], c[m], s[m], us[m], ut[m], u0[m], u1[m], u2[m]);
+      q.x += m2 * xv[m].x;
+      q.y += m2 * xv[m].y;
+      if (ok[m]) y[off + st[m].n] = q;
+    }
+  }
+}
+
+// Vectors per workgroup of the public batched kernels: the whole batch when the
+// lattice alone gives about 1024 workgroups or more, else fewer so that the launch
+// still has that many.
+static int pub_group(int ntiles, int batch) {
+  const long want = 1024;
+  const long per = (long)ntiles * batch / want;
+  return (int)std::max<long>(1, std::min<long>(batch, per));
 }
 
 // dS/dphi at every site: A: 2 Im[conj(eta(t)) s e^{i phi} z(t-1)],
@@ -652,6 +761,65 @@ __global__ __launch_bounds__(kBlock) void k_force(Geom g, const double* __restri
       const double F = 2.0 * (e.x * wi - e.y * wr);
       double* o = out + off + n;
       *o = accumulate ? *o + scale * F : scale * F;
+    }
+  }
+}
+
+// The same for a group of `per` vectors per workgroup: the temporal neighbour and
+// the phase of each site are evaluated once for the group.
+__global__ __launch_bounds__(kBlock) void k_force_grp(Geom g, const double* __restrict__ phi,
+                                                      const double2* __restrict__ eta,
+                                                      const double2* __restrict__ xi,
+                                                      const double2* __restrict__ sub, double scale, int accumulate,
+                                                      double* __restrict__ out, int ntiles, int per, int batch) {
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int grp = l / ntiles, tile = l - grp * ntiles;
+  const int b0 = grp * per, b1 = min(batch, b0 + per);
+  const int base = tile * kTile + threadIdx.x;
+  const int P2 = 2 * g.P;
+  // per site: the temporal neighbour and s e^{+-i phi}, shared by the vectors of the group
+  int tn[kSitesPerThread];
+  double ec[kSitesPerThread], es[kSitesPerThread];
+#pragma unroll
+  for (int m = 0; m < kSitesPerThread; ++m) {
+    const int n = min(base + m * kBlock, g.n - 1);
+    const uint32_t q2 = fdiv(fdiv((uint32_t)n, g.dL2), g.dL1);
+    const bool isA = (q2 & 1u) == 0;
+    const int t = (int)(q2 >> 1);
+    double sgn;
+    if (isA) {
+      const bool wrap = t == 0;
+      tn[m] = wrap ? n + (g.Nt - 1) * P2 : n - P2;
+      sgn = wrap ? -1.0 : 1.0;
+    } else {
+      const bool wrap = t == g.Nt - 1;
+      tn[m] = wrap ? n - (g.Nt - 1) * P2 : n + P2;
+      sgn = wrap ? -1.0 : 1.0;
+    }
+    double c, s;
+    cis64(phi[n], c, s);
+    ec[m] = sgn * c;
+    es[m] = sgn * (isA ? s : -s);
+  }
+  for (int b = b0; b < b1; ++b) {
+    const size_t off = (size_t)b * g.n;
+#pragma unroll
+    for (int m = 0; m < kSitesPerThread; ++m) {
+      const int n = base + m * kBlock;
+      if (n < g.n) {
+        const double2 e = eta[off + n];
+        double2 z = xi[off + tn[m]];
+        if (sub) {
+          const double2 v = sub[off + tn[m]];
+          z.x -= v.x;
+          z.y -= v.y;
+        }
+        // w = s e^{+-i phi} z ; F = 2 Im(conj(e) w)
+        const double wr = ec[m] * z.x - es[m] * z.y, wi = ec[m] * z.y + es[m] * z.x;
+        const double F = 2.0 * (e.x * wi - e.y * wr);
+        double* o = out + off + n;
+        *o = accumulate ? *o + scale * F : scale * F;
+      }
     }
   }
 }
@@ -1512,11 +1680,19 @@ static inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }
 hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
                         hipStream_t st) {
   const int nt = (g.n + kPubTile - 1) / kPubTile;
-  const dim3 grid(nt * batch), block(kBlock);
-  if (dag)
-    hipLaunchKernelGGL(k_apply<true>, grid, block, 0, st, g, phi, x, y, nt);
-  else
-    hipLaunchKernelGGL(k_apply<false>, grid, block, 0, st, g, phi, x, y, nt);
+  const int per = pub_group(nt, batch);
+  const dim3 grid(nt * ((batch + per - 1) / per)), block(kBlock);
+  if (per == 1) {
+    if (dag)
+      hipLaunchKernelGGL(k_apply<true>, grid, block, 0, st, g, phi, x, y, nt);
+    else
+      hipLaunchKernelGGL(k_apply<false>, grid, block, 0, st, g, phi, x, y, nt);
+  } else {
+    if (dag)
+      hipLaunchKernelGGL(k_apply_grp<true>, grid, block, 0, st, g, phi, x, y, nt, per, batch);
+    else
+      hipLaunchKernelGGL(k_apply_grp<false>, grid, block, 0, st, g, phi, x, y, nt, per, batch);
+  }
   return hipGetLastError();
 }
 
@@ -1524,8 +1700,14 @@ hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, doub
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi, double scale,
                         int accumulate, double* out, int batch, hipStream_t st, const double2* sub) {
   const int nt = tiles_of(g.n);
-  hipLaunchKernelGGL(k_force, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, eta, xi, sub, scale, accumulate, out,
-                     nt);
+  // 2048-site tiles: a quarter of the public kernels' workgroups per vector
+  const int per = pub_group(4 * nt, batch);
+  const dim3 grid(nt * ((batch + per - 1) / per)), block(kBlock);
+  if (per == 1)
+    hipLaunchKernelGGL(k_force, grid, block, 0, st, g, phi, eta, xi, sub, scale, accumulate, out, nt);
+  else
+    hipLaunchKernelGGL(k_force_grp, grid, block, 0, st, g, phi, eta, xi, sub, scale, accumulate, out, nt, per,
+                       batch);
   return hipGetLastError();
 }
 
@@ -1562,9 +1744,14 @@ hipError_t launch_ms_iter(const MsDesc* d, int ntiles, int it, hipStream_t st) {
 hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
                           const double2* x, double2* y, int batch, hipStream_t st) {
   const int nt = (g.n + kPubTile - 1) / kPubTile;
+  const int per = pub_group(nt, batch);
   Mu2Arr m;
   for (int b = 0; b < kMaxSys; ++b) m.v[b] = b < batch ? mu2_host[b] : 0.0;
-  hipLaunchKernelGGL(k_normal2_pub, dim3(nt * batch), dim3(kBlock), 0, st, g, phi, m, u, x, y, nt);
+  const dim3 grid(nt * ((batch + per - 1) / per)), block(kBlock);
+  if (per == 1)
+    hipLaunchKernelGGL(k_normal2_pub, grid, block, 0, st, g, phi, m, u, x, y, nt);
+  else
+    hipLaunchKernelGGL(k_normal2_grp, grid, block, 0, st, g, phi, m, u, x, y, nt, per, batch);
   return hipGetLastError();
 }
 
