@@ -120,6 +120,7 @@ class Engine {
 
  private:
   hipError_t host_phase(System* s, bool& progressed);
+  hipError_t group_phase(int phase, const std::vector<System*>& g);
   // A block of CG iterations enqueued for the systems of one precision, whose
   // convergence flags are read back asynchronously.
   struct Block {

@@ -3,6 +3,7 @@
 // of Appendix A (Algorithm A.1) for many systems at once, and the small Hessenberg
 // least-squares problem of the FGMRES update.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 
@@ -475,126 +476,160 @@ hipError_t Engine::host_phase(System* s, bool& progressed) {
       s->post = PH_F_POST_INIT;
       return hipSuccess;
     }
+    default:
+      return hipSuccess;
+  }
+}
+
+// One host-side transition for a group of systems at the same phase (and, in
+// FGMRES, the same Arnoldi step): one launch per kernel over the group's systems and
+// one read-back for all of them (the per-system arithmetic is that of a system alone).
+hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
+  const int j = g.front()->j;
+  switch (phase) {
     case PH_CG_CONFIRM: {
-      progressed = true;
-      LaunchList L = one(s);
-      L.pa[0] = tol * tol * s->bb;
-      L.pr[0] = 0.0;
-      L.pi[0] = std::max(1, o.max_iter - s->cg_total);
+      // FP64 true residual of the CG iterate; restart the CG from x if it misses tol
+      LaunchList L = list(g);
+      for (size_t q = 0; q < g.size(); ++q) {
+        const System* s = g[q];
+        L.pa[q] = s->opts.tol * s->opts.tol * s->bb;
+        L.pr[q] = 0.0;
+        L.pi[q] = std::max(1, s->opts.max_iter - s->cg_total);
+      }
       HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
-      s->info.applies++;
-      HUB_TRY(read_scal({s}));
-      const double rr = h_scal_[s->slot].red[1];
-      s->info.true_rel_resid = s->bb > 0 ? std::sqrt(rr / s->bb) : 0.0;
-      if (s->info.true_rel_resid <= tol) {
-        finish(s, HUB_OK);
-      } else if (s->cg_total >= o.max_iter || !std::isfinite(rr)) {
-        finish(s, HUB_ERR_NOCONV);
-      } else {
-        s->info.outer_iters++;
-        s->enq = 0;
-        s->gen++;
-        s->phase = PH_CG_ITER;
+      HUB_TRY(read_scal(g));
+      for (System* s : g) {
+        const hub_solve_opts& o = s->opts;
+        s->info.applies++;
+        const double rr = h_scal_[s->slot].red[1];
+        s->info.true_rel_resid = s->bb > 0 ? std::sqrt(rr / s->bb) : 0.0;
+        if (s->info.true_rel_resid <= o.tol) {
+          finish(s, HUB_OK);
+        } else if (s->cg_total >= o.max_iter || !std::isfinite(rr)) {
+          finish(s, HUB_ERR_NOCONV);
+        } else {
+          s->info.outer_iters++;
+          s->enq = 0;
+          s->gen++;
+          s->phase = PH_CG_ITER;
+        }
       }
       return hipSuccess;
     }
     case PH_F_POST_INIT: {
-      progressed = true;
-      std::vector<std::complex<double>> y{std::complex<double>(1.0, 0.0)};
-      HUB_TRY(upload_y(s, y));
-      LaunchList L = one(s);
-      HUB_TRY(launch_xupdate(d_desc_, L, 1, !o.use_x0, st_));
+      // x = z_0 (or x0 + z_0), r = b - A x, ERR = |r|
+      for (System* s : g) HUB_TRY(upload_y(s, {std::complex<double>(1.0, 0.0)}));
+      const LaunchList L = list(g);
+      HUB_TRY(launch_xupdate(d_desc_, L, 1, !g.front()->opts.use_x0, st_));
       HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
-      s->info.applies++;
-      HUB_TRY(read_scal({s}));
-      s->err = std::sqrt(h_scal_[s->slot].red[0]);
-      s->info.true_rel_resid = s->err / s->bnorm;
-      if (s->err <= tol * s->bnorm) {
-        finish(s, HUB_OK);
-        return hipSuccess;
+      HUB_TRY(read_scal(g));
+      for (System* s : g) {
+        const hub_solve_opts& o = s->opts;
+        s->info.applies++;
+        s->err = std::sqrt(h_scal_[s->slot].red[0]);
+        s->info.true_rel_resid = s->err / s->bnorm;
+        if (s->err <= o.tol * s->bnorm) {
+          finish(s, HUB_OK);
+          continue;
+        }
+        s->j = 0;
+        s->wnorm = s->err;
+        s->rnorm_cycle = s->err;
+        s->H.assign((size_t)(o.restart_m + 1) * o.restart_m, std::complex<double>(0.0));
+        s->phase = PH_F_ARNOLDI;
       }
-      s->j = 0;
-      s->wnorm = s->err;
-      s->rnorm_cycle = s->err;
-      s->H.assign((size_t)(o.restart_m + 1) * o.restart_m, std::complex<double>(0.0));
-      s->phase = PH_F_ARNOLDI;
       return hipSuccess;
     }
     case PH_F_ARNOLDI: {
-      progressed = true;
-      if (s->err < tol * s->bnorm || s->wnorm == 0.0 || !std::isfinite(s->wnorm)) {
-        s->phase = PH_F_LSQ;
-        return hipSuccess;
+      // v_j = w / |w|; z_j from the single-precision CG when TOL a |b| / ERR < 1, else z_j = v_j
+      std::vector<System*> act;
+      for (System* s : g) {
+        if (s->err < s->opts.tol * s->bnorm || s->wnorm == 0.0 || !std::isfinite(s->wnorm))
+          s->phase = PH_F_LSQ;
+        else
+          act.push_back(s);
       }
-      const int j = s->j;
-      const double ratio = tol * o.inner_a * s->bnorm / s->err;
-      LaunchList L = one(s);
-      L.pa[0] = 1.0 / s->wnorm;
-      L.pj[0] = S_Z0 + j;
-      if (ratio < 1.0) {
-        const double tau = std::max(ratio, o.inner_floor);
-        L.pr[0] = tau * tau;
-        L.pi[0] = o.inner_max_iter;
-        HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
-        s->enq = 0;
-        s->gen++;
-        s->phase = PH_F_INNER;
-        s->post = PH_F_POST_ARNOLDI;
-      } else {
-        L.pr[0] = 0.0;
-        L.pi[0] = 0;
-        HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
-        s->phase = PH_F_POST_ARNOLDI;
+      if (act.empty()) return hipSuccess;
+      LaunchList L = list(act);
+      for (size_t q = 0; q < act.size(); ++q) {
+        const System* s = act[q];
+        const hub_solve_opts& o = s->opts;
+        const double ratio = o.tol * o.inner_a * s->bnorm / s->err;
+        L.pa[q] = 1.0 / s->wnorm;
+        L.pj[q] = S_Z0 + j;
+        if (ratio < 1.0) {
+          const double tau = std::max(ratio, o.inner_floor);
+          L.pr[q] = tau * tau;
+          L.pi[q] = o.inner_max_iter;
+        } else {
+          L.pr[q] = 0.0;
+          L.pi[q] = 0;
+        }
+      }
+      HUB_TRY(launch_prep_inner(d_desc_, L, S_R, S_V0 + j, st_));
+      for (size_t q = 0; q < act.size(); ++q) {
+        System* s = act[q];
+        if (L.pi[q] > 0) {
+          s->enq = 0;
+          s->gen++;
+          s->phase = PH_F_INNER;
+          s->post = PH_F_POST_ARNOLDI;
+        } else {
+          s->phase = PH_F_POST_ARNOLDI;
+        }
       }
       return hipSuccess;
     }
     case PH_F_POST_ARNOLDI: {
-      progressed = true;
-      const int j = s->j;
-      const int m = o.restart_m;
-      LaunchList L = one(s);
+      // w = A z_j, classical Gram-Schmidt against v_0 .. v_j, h_{j+1,j} = |w|, ERR *= |w|
+      const LaunchList L = list(g);
       HUB_TRY(launch_normal_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
       HUB_TRY(launch_multidot(d_desc_, L, S_R, S_V0, j + 1, 0, st_));
       HUB_TRY(launch_cgs(d_desc_, L, S_R, S_V0, j + 1, 0, 2 * (j + 1), st_));
-      s->info.applies++;
-      HUB_TRY(read_scal({s}));
-      const Scal& sc = h_scal_[s->slot];
-      for (int i = 0; i <= j; ++i) s->H[(size_t)j * (m + 1) + i] = {sc.red[2 * i], sc.red[2 * i + 1]};
-      const double hn = std::sqrt(std::max(sc.red[2 * (j + 1)], 0.0));
-      s->H[(size_t)j * (m + 1) + j + 1] = hn;
-      s->wnorm = hn;
-      s->err *= hn;
-      s->j = j + 1;
-      s->phase = (s->j == m) ? PH_F_LSQ : PH_F_ARNOLDI;
+      HUB_TRY(read_scal(g));
+      for (System* s : g) {
+        const int m = s->opts.restart_m;
+        s->info.applies++;
+        const Scal& sc = h_scal_[s->slot];
+        for (int i = 0; i <= j; ++i) s->H[(size_t)j * (m + 1) + i] = {sc.red[2 * i], sc.red[2 * i + 1]};
+        const double hn = std::sqrt(std::max(sc.red[2 * (j + 1)], 0.0));
+        s->H[(size_t)j * (m + 1) + j + 1] = hn;
+        s->wnorm = hn;
+        s->err *= hn;
+        s->j = j + 1;
+        s->phase = (s->j == m) ? PH_F_LSQ : PH_F_ARNOLDI;
+      }
       return hipSuccess;
     }
     case PH_F_LSQ: {
-      progressed = true;
-      const int k = s->j;
-      const int m = o.restart_m;
-      LaunchList L = one(s);
+      // y = argmin |(|r|, 0, ..) - H y|, x += sum y_i z_i, true residual, restart or stop
+      const int k = j;
+      const LaunchList L = list(g);
       if (k > 0) {
-        std::vector<std::complex<double>> y = hessenberg_lsq(s->H, m + 1, k, s->rnorm_cycle);
-        HUB_TRY(upload_y(s, y));
+        for (System* s : g)
+          HUB_TRY(upload_y(s, hessenberg_lsq(s->H, s->opts.restart_m + 1, k, s->rnorm_cycle)));
         HUB_TRY(launch_xupdate(d_desc_, L, k, false, st_));
       }
       HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
-      s->info.applies++;
-      s->cycles++;
-      s->info.outer_iters = s->cycles;
-      HUB_TRY(read_scal({s}));
-      s->err = std::sqrt(h_scal_[s->slot].red[0]);
-      s->info.true_rel_resid = s->err / s->bnorm;
-      if (s->err <= tol * s->bnorm) {
-        finish(s, HUB_OK);
-      } else if (s->cycles >= std::min(o.max_iter, 1000) || !std::isfinite(s->err) || k == 0) {
-        finish(s, HUB_ERR_NOCONV);
-      } else {
-        s->j = 0;
-        s->wnorm = s->err;
-        s->rnorm_cycle = s->err;
-        std::fill(s->H.begin(), s->H.end(), std::complex<double>(0.0));
-        s->phase = PH_F_ARNOLDI;
+      HUB_TRY(read_scal(g));
+      for (System* s : g) {
+        const hub_solve_opts& o = s->opts;
+        s->info.applies++;
+        s->cycles++;
+        s->info.outer_iters = s->cycles;
+        s->err = std::sqrt(h_scal_[s->slot].red[0]);
+        s->info.true_rel_resid = s->err / s->bnorm;
+        if (s->err <= o.tol * s->bnorm) {
+          finish(s, HUB_OK);
+        } else if (s->cycles >= std::min(o.max_iter, 1000) || !std::isfinite(s->err) || k == 0) {
+          finish(s, HUB_ERR_NOCONV);
+        } else {
+          s->j = 0;
+          s->wnorm = s->err;
+          s->rnorm_cycle = s->err;
+          std::fill(s->H.begin(), s->H.end(), std::complex<double>(0.0));
+          s->phase = PH_F_ARNOLDI;
+        }
       }
       return hipSuccess;
     }
@@ -734,16 +769,31 @@ hipError_t Engine::step() {
       q.erase(q.begin());
     }
   }
-  // 3. host-side phases of the systems that are not iterating
+  // 3. host-side phases of the systems that are not iterating: the start system by
+  //    system, the FP64 CG confirmation and the FGMRES transitions in groups of
+  //    systems at the same phase and Arnoldi step
   bool progressed = true;
   while (progressed) {
     progressed = false;
     for (System* s : slots_) {
-      if (!s || s->done) continue;
+      if (!s || s->done || s->phase != PH_NEW) continue;
       bool p = false;
       HUB_TRY(host_phase(s, p));
       progressed = progressed || p;
       if (s->done && s->on_done) s->on_done(s);
+    }
+    for (int ph : {(int)PH_CG_CONFIRM, (int)PH_F_POST_INIT, (int)PH_F_LSQ, (int)PH_F_POST_ARNOLDI,
+                   (int)PH_F_ARNOLDI}) {
+      // key: Arnoldi step (and, at the start, whether x0 is used: the update kernel's mode)
+      std::map<int, std::vector<System*>> groups;
+      for (System* s : slots_)
+        if (s && !s->done && s->phase == ph) groups[2 * s->j + (s->opts.use_x0 ? 1 : 0)].push_back(s);
+      for (auto& kv : groups) {
+        HUB_TRY(group_phase(ph, kv.second));
+        progressed = true;
+        for (System* s : kv.second)
+          if (s->done && s->on_done) s->on_done(s);
+      }
     }
     bool all_wait = true;
     for (System* s : slots_)
