@@ -119,7 +119,7 @@ class Engine {
   hipError_t finalize(System* s, const double2* chi, double* dSdphi, double* S);
 
  private:
-  hipError_t host_phase(System* s, bool& progressed);
+  // One host-side transition of a group of systems at the same phase.
   hipError_t group_phase(int phase, const std::vector<System*>& g);
   // A block of CG iterations enqueued for the systems of one precision, whose
   // convergence flags are read back asynchronously.

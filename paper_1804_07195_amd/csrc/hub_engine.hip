@@ -404,89 +404,98 @@ void Engine::finish(System* s, hub_status st) {
   s->info.converged = st == HUB_OK ? 1 : 0;
 }
 
-// One host-side transition of a system that is not iterating.
-hipError_t Engine::host_phase(System* s, bool& progressed) {
-  const hub_solve_opts& o = s->opts;
-  const double tol = o.tol;
-  switch (s->phase) {
-    case PH_NEW: {
-      progressed = true;
-      if (!is_fgmres(o)) {
-        if (!o.use_x0) {
-          LaunchList L = one(s);
-          L.pa[0] = 0.0;
-          L.pr[0] = tol * tol;
-          L.pi[0] = o.max_iter;
-          HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_CG_SETUP, st_));
-        } else {
-          LaunchList L = one(s);
-          HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
-          HUB_TRY(read_scal({s}));
-          s->bb = h_scal_[s->slot].red[0];
-          L.pa[0] = tol * tol * s->bb;
-          L.pr[0] = 0.0;
-          L.pi[0] = o.max_iter;
-          HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
-          s->info.applies++;
-        }
-        s->enq = 0;
-        s->gen++;
-        s->phase = PH_CG_ITER;
-        return hipSuccess;
-      }
-      // FGMRES: r = b (or b - A x0), |b|
-      LaunchList L = one(s);
-      if (!o.use_x0) {
-        HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_STORE, st_));
-        HUB_TRY(read_scal({s}));
-        s->bb = h_scal_[s->slot].red[0];
-        s->err = std::sqrt(s->bb);
-      } else {
-        HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
-        HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 2, st_));
-        HUB_TRY(read_scal({s}));
-        s->bb = h_scal_[s->slot].red[0];
-        s->err = std::sqrt(h_scal_[s->slot].red[2]);
-        s->info.applies++;
-      }
-      s->bnorm = std::sqrt(s->bb);
-      if (s->bnorm == 0.0) {
-        // b = 0: x = 0 exactly
-        LaunchList Lz = one(s);
-        HUB_TRY(launch_cg_init_zero(d_desc_, Lz, RED_STORE, st_));
-        s->info.true_rel_resid = 0.0;
-        finish(s, HUB_OK);
-        return hipSuccess;
-      }
-      if (s->err <= tol * s->bnorm) {
-        s->info.true_rel_resid = s->err / s->bnorm;
-        finish(s, HUB_OK);
-        return hipSuccess;
-      }
-      // initial single-precision solve on r (Algorithm A.1, first line)
-      const double tau = std::max(std::min(tol * o.inner_a * s->bnorm / s->err, 1.0), o.inner_floor);
-      L.pa[0] = 1.0;
-      L.pr[0] = tau * tau;
-      L.pi[0] = o.inner_max_iter;
-      L.pj[0] = S_Z0;
-      HUB_TRY(launch_prep_inner(d_desc_, L, S_R, -1, st_));
-      s->enq = 0;
-      s->gen++;
-      s->phase = PH_F_INNER;
-      s->post = PH_F_POST_INIT;
-      return hipSuccess;
-    }
-    default:
-      return hipSuccess;
-  }
-}
-
 // One host-side transition for a group of systems at the same phase (and, in
 // FGMRES, the same Arnoldi step): one launch per kernel over the group's systems and
 // one read-back for all of them (the per-system arithmetic is that of a system alone).
 hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
   const int j = g.front()->j;
   switch (phase) {
+    case PH_NEW: {
+      // the group shares the solver and whether x0 is used
+      const hub_solve_opts& og = g.front()->opts;
+      LaunchList L = list(g);
+      if (!is_fgmres(og)) {
+        // FP64 CG: r = b - A x (x = 0 or x0) and the CG start
+        if (!og.use_x0) {
+          for (size_t q = 0; q < g.size(); ++q) {
+            L.pa[q] = 0.0;
+            L.pr[q] = g[q]->opts.tol * g[q]->opts.tol;
+            L.pi[q] = g[q]->opts.max_iter;
+          }
+          HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_CG_SETUP, st_));
+        } else {
+          HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
+          HUB_TRY(read_scal(g));
+          for (size_t q = 0; q < g.size(); ++q) {
+            System* s = g[q];
+            s->bb = h_scal_[s->slot].red[0];
+            L.pa[q] = s->opts.tol * s->opts.tol * s->bb;
+            L.pr[q] = 0.0;
+            L.pi[q] = s->opts.max_iter;
+            s->info.applies++;
+          }
+          HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+        }
+        for (System* s : g) {
+          s->enq = 0;
+          s->gen++;
+          s->phase = PH_CG_ITER;
+        }
+        return hipSuccess;
+      }
+      // FGMRES: r = b (or b - A x0), |b|
+      if (!og.use_x0) {
+        HUB_TRY(launch_cg_init_zero(d_desc_, L, RED_STORE, st_));
+      } else {
+        HUB_TRY(launch_multidot(d_desc_, L, S_B, S_B, 1, 0, st_));
+        HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 2, st_));
+      }
+      HUB_TRY(read_scal(g));
+      std::vector<System*> run, zero;
+      for (System* s : g) {
+        const Scal& sc = h_scal_[s->slot];
+        s->bb = sc.red[0];
+        s->err = og.use_x0 ? std::sqrt(sc.red[2]) : std::sqrt(s->bb);
+        if (og.use_x0) s->info.applies++;
+        s->bnorm = std::sqrt(s->bb);
+        if (s->bnorm == 0.0) {
+          zero.push_back(s);
+        } else if (s->err <= s->opts.tol * s->bnorm) {
+          s->info.true_rel_resid = s->err / s->bnorm;
+          finish(s, HUB_OK);
+        } else {
+          run.push_back(s);
+        }
+      }
+      if (!zero.empty()) {
+        // b = 0: x = 0 exactly
+        HUB_TRY(launch_cg_init_zero(d_desc_, list(zero), RED_STORE, st_));
+        for (System* s : zero) {
+          s->info.true_rel_resid = 0.0;
+          finish(s, HUB_OK);
+        }
+      }
+      if (run.empty()) return hipSuccess;
+      // initial single-precision solve on r (Algorithm A.1, first line)
+      LaunchList R = list(run);
+      for (size_t q = 0; q < run.size(); ++q) {
+        const System* s = run[q];
+        const hub_solve_opts& o = s->opts;
+        const double tau = std::max(std::min(o.tol * o.inner_a * s->bnorm / s->err, 1.0), o.inner_floor);
+        R.pa[q] = 1.0;
+        R.pr[q] = tau * tau;
+        R.pi[q] = o.inner_max_iter;
+        R.pj[q] = S_Z0;
+      }
+      HUB_TRY(launch_prep_inner(d_desc_, R, S_R, -1, st_));
+      for (System* s : run) {
+        s->enq = 0;
+        s->gen++;
+        s->phase = PH_F_INNER;
+        s->post = PH_F_POST_INIT;
+      }
+      return hipSuccess;
+    }
     case PH_CG_CONFIRM: {
       // FP64 true residual of the CG iterate; restart the CG from x if it misses tol
       LaunchList L = list(g);
@@ -769,25 +778,19 @@ hipError_t Engine::step() {
       q.erase(q.begin());
     }
   }
-  // 3. host-side phases of the systems that are not iterating: the start system by
-  //    system, the FP64 CG confirmation and the FGMRES transitions in groups of
-  //    systems at the same phase and Arnoldi step
+  // 3. host-side phases of the systems that are not iterating, in groups of systems
+  //    at the same phase (and Arnoldi step)
   bool progressed = true;
   while (progressed) {
     progressed = false;
-    for (System* s : slots_) {
-      if (!s || s->done || s->phase != PH_NEW) continue;
-      bool p = false;
-      HUB_TRY(host_phase(s, p));
-      progressed = progressed || p;
-      if (s->done && s->on_done) s->on_done(s);
-    }
-    for (int ph : {(int)PH_CG_CONFIRM, (int)PH_F_POST_INIT, (int)PH_F_LSQ, (int)PH_F_POST_ARNOLDI,
+    for (int ph : {(int)PH_NEW, (int)PH_CG_CONFIRM, (int)PH_F_POST_INIT, (int)PH_F_LSQ, (int)PH_F_POST_ARNOLDI,
                    (int)PH_F_ARNOLDI}) {
-      // key: Arnoldi step (and, at the start, whether x0 is used: the update kernel's mode)
+      // key: Arnoldi step, solver and whether x0 is used (the start's and the first
+      // update's kernels depend on them)
       std::map<int, std::vector<System*>> groups;
       for (System* s : slots_)
-        if (s && !s->done && s->phase == ph) groups[2 * s->j + (s->opts.use_x0 ? 1 : 0)].push_back(s);
+        if (s && !s->done && s->phase == ph)
+          groups[4 * s->j + (is_fgmres(s->opts) ? 2 : 0) + (s->opts.use_x0 ? 1 : 0)].push_back(s);
       for (auto& kv : groups) {
         HUB_TRY(group_phase(ph, kv.second));
         progressed = true;
