@@ -127,7 +127,8 @@ class Engine {
     bool single = false;
     int k = 0;
     int buf = 0;
-    std::vector<System*> v;
+    std::vector<System*> v;             // grouped by tile class
+    std::vector<int> cls_end;           // end of each class in v
     std::vector<int> gen;               // System::gen of each system at enqueue
     std::vector<std::vector<int>> its;  // iteration index per launch and system (profiling)
     std::vector<hipEvent_t> kev;        // kernel start/stop events (profiling)
@@ -139,6 +140,7 @@ class Engine {
   hipError_t upload_desc(System* s);
   hipError_t upload_y(System* s, const std::vector<std::complex<double>>& y);
   LaunchList one(System* s) const;
+  // Launch list over v (systems of one tile class).
   LaunchList list(const std::vector<System*>& v) const;
   void finish(System* s, hub_status st);
 

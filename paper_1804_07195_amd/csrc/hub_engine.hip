@@ -236,7 +236,7 @@ static bool is_fgmres(const hub_solve_opts& o) { return o.solver == HUB_FGMRES_M
 
 size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
   const size_t n = (size_t)g.n;
-  const size_t part = Pool::rounded((size_t)ntiles_of(g.n) * (kMaxRed + 2) * sizeof(double));
+  const size_t part = Pool::rounded((size_t)tiles_of_spt(g.n, spt_of(g.n)) * (kMaxRed + 2) * sizeof(double));
   // vectors + the phase tables that `add` computes when the caller brings none
   // (FP64 phase n * 16; the mixed solver's float angle n * 4)
   if (!is_fgmres(o)) return 5 * Pool::rounded(n * 16) + part;
@@ -262,7 +262,8 @@ bool Engine::add(System* s) {
   d.g = s->g;
   d.mu2 = s->mu2;
   d.phi = s->phi;
-  d.ntiles = ntiles_of(s->g.n);
+  d.spt = spt_of(s->g.n);
+  d.ntiles = tiles_of_spt(s->g.n, d.spt);
   d.sc = d_scal_ + slot;
   auto get = [&](size_t bytes) -> void* {
     void* p = pool_->alloc(bytes, st_);
@@ -374,6 +375,8 @@ LaunchList Engine::list(const std::vector<System*>& v) const {
   std::memset(&L, 0, sizeof(L));
   L.scal = d_scal_;
   L.nsys = (int)v.size();
+  // every system of a list has the same tile class (callers group them)
+  L.spt = v.empty() ? kSitesPerThread : v.front()->desc.spt;
   int acc = 0;
   for (int k = 0; k < L.nsys; ++k) {
     L.tile_begin[k] = acc;
@@ -665,18 +668,39 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     }
   }
   if (v.empty()) return hipSuccess;
+  // systems by the tile size of their CG stages: one launch per size class
+  std::vector<System*> ordered;
+  std::vector<int> cls_spt, cls_end;
+  for (int spt : {(int)kSitesPerThread, (int)kSmallSpt}) {
+    for (System* s : v)
+      if (s->desc.spt == spt) ordered.push_back(s);
+    if (!ordered.empty() && (cls_end.empty() || (int)ordered.size() > cls_end.back())) {
+      cls_spt.push_back(spt);
+      cls_end.push_back((int)ordered.size());
+    }
+    if (kSmallSpt == kSitesPerThread) break;
+  }
+  v = ordered;
+  const int ncls = (int)cls_spt.size();
   Block b;
   b.single = single;
   b.k = k;
   b.v = v;
+  b.cls_end = cls_end;
   for (System* s : v) b.gen.push_back(s->gen);
   b.buf = next_buf_[single ? 1 : 0];
   next_buf_[single ? 1 : 0] ^= 1;
-  LaunchList L = list(v);
-  // The solution slot of the initial single-precision solve is S_Z0 (j = 0 then).
-  for (size_t q = 0; q < v.size(); ++q) L.pi[q] = single ? S_Z0 + v[q]->j : S_X;
+  std::vector<LaunchList> Ls;
+  for (int c = 0; c < ncls; ++c) {
+    const int q0 = c == 0 ? 0 : cls_end[c - 1];
+    std::vector<System*> vc(v.begin() + q0, v.begin() + cls_end[c]);
+    LaunchList L = list(vc);
+    // The solution slot of the initial single-precision solve is S_Z0 (j = 0 then).
+    for (size_t q = 0; q < vc.size(); ++q) L.pi[q] = single ? S_Z0 + vc[q]->j : S_X;
+    Ls.push_back(L);
+  }
   if (profiling_) {
-    for (int e = 0; e < 4 * k; ++e) {
+    for (int e = 0; e < 4 * k * ncls; ++e) {
       if (events_.empty()) {
         hipEvent_t ev;
         HUB_TRY(hipEventCreate(&ev));
@@ -687,14 +711,22 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     }
   }
   for (int it = 0; it < k; ++it) {
-    for (size_t q = 0; q < v.size(); ++q) L.it[q] = v[q]->enq++;
+    std::vector<int> its(v.size());
+    for (size_t q = 0; q < v.size(); ++q) its[q] = v[q]->enq++;
+    for (int c = 0; c < ncls; ++c) {
+      const int q0 = c == 0 ? 0 : cls_end[c - 1];
+      for (int q = q0; q < cls_end[c]; ++q) Ls[c].it[q - q0] = its[q];
+    }
     if (!profiling_) {
-      HUB_TRY(launch_cg_iter(d_desc_, L, single, st_));
+      for (int c = 0; c < ncls; ++c) HUB_TRY(launch_cg_iter(d_desc_, Ls[c], single, st_));
       continue;
     }
-    b.its.emplace_back(L.it, L.it + v.size());
-    HUB_TRY(launch_cg_stage(d_desc_, L, single, 1, st_, b.kev[4 * it], b.kev[4 * it + 1]));
-    HUB_TRY(launch_cg_stage(d_desc_, L, single, 2, st_, b.kev[4 * it + 2], b.kev[4 * it + 3]));
+    b.its.push_back(its);
+    for (int stage = 1; stage <= 2; ++stage)
+      for (int c = 0; c < ncls; ++c) {
+        const int e = 4 * (it * ncls + c) + 2 * (stage - 1);
+        HUB_TRY(launch_cg_stage(d_desc_, Ls[c], single, stage, st_, b.kev[e], b.kev[e + 1]));
+      }
   }
   int lo = kMaxSys, hi = -1;
   for (System* s : v) {
@@ -721,20 +753,25 @@ hipError_t Engine::finish_block(Block& b) {
   if (profiling_ && !b.kev.empty()) {
     // A system did work in the launch of iteration `it` iff it < its final count
     // (or it is still iterating).
+    const int ncls = (int)b.cls_end.size();
     for (int it = 0; it < b.k; ++it) {
-      for (int stage = 0; stage < 2; ++stage) {
-        double bytes = 0.0;
-        for (size_t q = 0; q < b.v.size(); ++q) {
-          const Scal& sc = flags[b.v[q]->slot];
-          const int its = b.its[it][q];
-          if (sc.active || its < sc.iters) bytes += (double)b.v[q]->g.n * cg_bytes(single, stage + 1, its);
+      for (int c = 0; c < ncls; ++c) {
+        const int q0 = c == 0 ? 0 : b.cls_end[c - 1];
+        for (int stage = 0; stage < 2; ++stage) {
+          double bytes = 0.0;
+          for (int q = q0; q < b.cls_end[c]; ++q) {
+            const Scal& sc = flags[b.v[q]->slot];
+            const int its = b.its[it][q];
+            if (sc.active || its < sc.iters) bytes += (double)b.v[q]->g.n * cg_bytes(single, stage + 1, its);
+          }
+          const int e = 4 * (it * ncls + c) + 2 * stage;
+          float ms = 0.0f;
+          HUB_TRY(hipEventElapsedTime(&ms, b.kev[e], b.kev[e + 1]));
+          KernelStat& ks = stat[single ? 1 : 0][stage];
+          ks.launches++;
+          ks.ms += ms;
+          ks.bytes += bytes;
         }
-        float ms = 0.0f;
-        HUB_TRY(hipEventElapsedTime(&ms, b.kev[4 * it + 2 * stage], b.kev[4 * it + 2 * stage + 1]));
-        KernelStat& ks = stat[single ? 1 : 0][stage];
-        ks.launches++;
-        ks.ms += ms;
-        ks.bytes += bytes;
       }
     }
   }
@@ -785,12 +822,14 @@ hipError_t Engine::step() {
     progressed = false;
     for (int ph : {(int)PH_NEW, (int)PH_CG_CONFIRM, (int)PH_F_POST_INIT, (int)PH_F_LSQ, (int)PH_F_POST_ARNOLDI,
                    (int)PH_F_ARNOLDI}) {
-      // key: Arnoldi step, solver and whether x0 is used (the start's and the first
-      // update's kernels depend on them)
+      // key: Arnoldi step, solver, whether x0 is used (the start's and the first
+      // update's kernels depend on them) and tile class (one per launch)
       std::map<int, std::vector<System*>> groups;
       for (System* s : slots_)
         if (s && !s->done && s->phase == ph)
-          groups[4 * s->j + (is_fgmres(s->opts) ? 2 : 0) + (s->opts.use_x0 ? 1 : 0)].push_back(s);
+          groups[8 * s->j + (s->desc.spt == kSmallSpt ? 4 : 0) + (is_fgmres(s->opts) ? 2 : 0) +
+                 (s->opts.use_x0 ? 1 : 0)]
+              .push_back(s);
       for (auto& kv : groups) {
         HUB_TRY(group_phase(ph, kv.second));
         progressed = true;

@@ -80,8 +80,8 @@ struct SysDesc {
   double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
   double* part1;         // per-tile partials of CG stage 1 [ntiles]
   double* part2;         // per-tile partials of CG stage 2 [ntiles]
-  int ntiles;
-  int pad;
+  int ntiles;            // tiles of kBlock * spt sites
+  int spt;               // sites per thread of every solver kernel of this system (tile class)
   void* vec[kMaxSlots];  // vector slots (type fixed by the slot's role)
 };
 
@@ -127,6 +127,8 @@ struct LaunchList {
   Scal* scal;           // the engine's Scal array: system slot k uses scal[k]
   int nsys;
   int total_tiles;
+  int spt;              // tile class of every system of the list (sites per thread)
+  int pad;
   int tile_begin[kMaxSys + 1];
   int sys[kMaxSys];     // index into the SysDesc array
   double pa[kMaxSys];   // per-system kernel parameters (meaning set by the kernel)
@@ -150,6 +152,17 @@ struct CgList {
   int it[N];   // CG iteration index
 };
 constexpr int kSmallCg = 4;
+
+// Tile class of a system: sites per thread of all its solver kernels.  Large systems
+// take kSitesPerThread (2048-site tiles: fewer workgroups, fixed costs spread over more
+// sites); a system below kBigSites takes kSmallSpt, so that its grids have enough
+// workgroups to hide latency (the CG stages of a 48x48x64 system run 9-13% faster with
+// 1024-site tiles, those of a 102x102x64 system 7% slower).  Launch lists hold systems
+// of one class.
+constexpr int kSmallSpt = 4;
+constexpr int kBigSites = 300 * kTile;
+inline int spt_of(int n) { return n >= kBigSites ? kSitesPerThread : kSmallSpt; }
+inline int tiles_of_spt(int n, int spt) { return (n + kBlock * spt - 1) / (kBlock * spt); }
 
 // Vector slot roles.  FP64 slots hold double2 [n]; C64 slots hold float2 [n].
 enum Slot : int {
@@ -197,6 +210,7 @@ hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double
 
 // Batched solver kernels over the systems of a LaunchList (descriptors in `sys`).
 // FP64 or C64 CG iteration in two stages (see hub_kernels.hip).
+// The batched solver launchers below take systems of one tile class (L.spt).
 hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st);
 // One stage (1 or 2) of the CG iteration.  With events, the launch records the
 // kernel's own start and end timestamps into them (hipExtLaunchKernel).

@@ -422,18 +422,18 @@ __device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
   return s;
 }
 
-// Apply M (DAG = false) or M^dagger to the kSitesPerThread/2 site pairs of this
-// thread in a tile: pairs base_pair + threadIdx.x + m*kBlock.  ld2(k) loads the raw
+// Apply M (DAG = false) or M^dagger to the TOTAL/2 site pairs of this thread in a
+// tile of kBlock * TOTAL sites: pairs base_pair + threadIdx.x + m*kBlock.  ld2(k) loads the raw
 // input at k, k+1 and ld1(k) at k; after `mid()` (see stencil_sites), cook2 / cook1
 // turn them into C64x2 / float2 inputs; post(n, y, self, pre) per pair.
-template <bool DAG, typename Phi, typename Ld2, typename Ld1, typename Cook2, typename Cook1, typename Pre,
-          typename Mid, typename Post>
+template <bool DAG, int TOTAL = kSitesPerThread, typename Phi, typename Ld2, typename Ld1, typename Cook2,
+          typename Cook1, typename Pre, typename Mid, typename Post>
 __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int tile, Ld2 ld2, Ld1 ld1,
                                               Cook2 cook2, Cook1 cook1, Pre pre, Mid mid, Post post) {
   using PV = decltype(pre(0));
   using R2 = decltype(ld2(0));
   using R1 = decltype(ld1(0));
-  constexpr int NPT = kSitesPerThread / 2;  // pairs per thread
+  constexpr int NPT = TOTAL / 2;  // pairs per thread
   constexpr int NP = HUB_PAIRS_PER_ROUND < NPT ? HUB_PAIRS_PER_ROUND : NPT;  // pairs in flight per round
   static_assert(NPT % NP == 0, "rounds must divide the pairs");
 #pragma unroll
@@ -442,7 +442,7 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
   bool ok[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    int n = tile * kTile + 2 * (threadIdx.x + (q0 + m) * kBlock);
+    int n = tile * (kBlock * TOTAL) + 2 * (threadIdx.x + (q0 + m) * kBlock);
     ok[m] = n < g.n;
     n = ok[m] ? n : g.n - 2;
     st[m] = pair_index<DAG>(g, n);
@@ -886,14 +886,16 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
 // ---------------------------------------------------------------------------
 // Batched solver kernels (descriptor + launch list).
 // ---------------------------------------------------------------------------
-#define HUB_PROLOGUE                                   \
+// Prologue of the batched solver kernels: the system and tile of this workgroup,
+// tiles of TILE sites (every kernel of a system uses the tile size of its class).
+#define HUB_PROLOGUE_T(TILE)                           \
   const int lt = xcd_remap(blockIdx.x, gridDim.x);     \
   const int kk = find_sys(L, lt);                      \
   const SysDesc* __restrict__ d = sys + L.sys[kk];     \
   const int tile = lt - L.tile_begin[kk];              \
   Scal* sc = L.scal + L.sys[kk];                       \
   const Geom g = d->g;                                 \
-  const int base = tile * kTile + threadIdx.x;
+  const int base = tile * (TILE) + threadIdx.x;
 
 // CG stage 1 of iteration it = L.it[kk]:
 //   |r_it|^2 from the stage-2 partials of iteration it-1 (it > 0) and the stopping
@@ -909,10 +911,11 @@ struct RP {
   C r, p;
 };
 
-template <typename R, typename LL>
+template <typename R, typename LL, int SPT>
 __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys, LL L, int sR, int sP, int sU) {
   using C = typename V2<R>::T;
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   if (!load_active(sc)) return;
   const int it = L.it[kk];
   const R mu2 = (R)d->mu2;
@@ -952,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
       if (it == 0) {
         auto ld2 = [=](int k) { return r.pair(k); };
         auto ld1 = [=](int k) { return r[k]; };
-        stencil_pairs<true>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, NoMid{}, post2);
+        stencil_pairs<true, SPT>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, NoMid{}, post2);
       } else {
         auto ld2 = [=](int k) { return RP<C64x2>{r.pair(k), po.pair(k)}; };
         auto ld1 = [=](int k) { return RP<C>{r[k], po[k]}; };
@@ -970,7 +973,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
           o.y = v.r.y + beta * v.p.y;
           return o;
         };
-        stencil_pairs<true>(g, phi, tile, ld2, ld1, cook2, cook1, pre2, mid, post2);
+        stencil_pairs<true, SPT>(g, phi, tile, ld2, ld1, cook2, cook1, pre2, mid, post2);
       }
       done = true;
     }
@@ -984,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
     };
     if (it == 0) {
       auto ld = [=](int k) { return r[k]; };
-      stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
     } else {
       auto ld = [=](int k) { return RP<C>{r[k], po[k]}; };
       auto cook = [&](RP<C> v) {
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
         o.y = v.r.y + beta * v.p.y;
         return o;
       };
-      stencil_sites<R, true, Spt<R>::v>(g, phi, base, ld, cook, pre, mid, post);
+      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, ld, cook, pre, mid, post);
     }
   }
   // a system that met its stopping test in `mid` writes no partial (none is read)
@@ -1001,8 +1004,8 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
     if (it & 1) {
       const R a = (R)sc->alpha[(it - 1) & 1];
       const Vec<C> x(d->vec[L.pi[kk]]);
-      const int end = min((tile + 1) * kTile, g.n);
-      for (int k = tile * kTile + (int)threadIdx.x; k < end; k += kBlock) {
+      const int end = min((tile + 1) * TILE, g.n);
+      for (int k = tile * TILE + (int)threadIdx.x; k < end; k += kBlock) {
         const C pv = po[k];
         C xv = x[k];
         xv.x = fma(a, pv.x, xv.x);
@@ -1027,10 +1030,11 @@ template <typename C, bool UPD>
 struct Own {
   C p, r, x, q;  // x, q (p_{it-1}) loaded only when UPD
 };
-template <typename R, typename LL>
+template <typename R, typename LL, int SPT>
 __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys, LL L, int sR, int sP, int sU) {
   using C = typename V2<R>::T;
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   const int act = load_active(sc);
   if (act != 1) {
     if (act == 2 && tile == 0 && threadIdx.x == 0) store_active(sc, 0);
@@ -1084,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
           }
           acc += norm2<R>(rv.a) + norm2<R>(rv.b);
         };
-        stencil_pairs<false>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
+        stencil_pairs<false, SPT>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
         return;
       }
     }
@@ -1112,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
       }
       acc += norm2<R>(rv);
     };
-    stencil_sites<R, false, Spt<R>::v>(g, phi, base, ld, Same{}, pre, mid, post);
+    stencil_sites<R, false, Spt<R>::v, SPT>(g, phi, base, ld, Same{}, pre, mid, post);
   };
   if (it & 1)
     run(std::true_type{});
@@ -1447,10 +1451,11 @@ __device__ __forceinline__ double2 normal12(const Geom& g, const PhasePhi<double
 
 // out = [b -] (M M^dagger + mu2) in, FP64 arithmetic (in: FP64 or complex64 slot),
 // partial |out|^2 (mode != RED_NONE).  One pass of the 12-point form.
-template <typename Tin>
+template <typename Tin, int SPT>
 __global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restrict__ sys, LaunchList L, int s_in,
                                                         int s_b, int s_out, int mode) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   (void)sc;
   const Vec<Tin> in(d->vec[s_in]);
   const bool has_b = s_b >= 0;
@@ -1460,7 +1465,7 @@ __global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restric
   auto ld = [=](int k) { return to_c128<Tin>(in[k]); };
   double acc = 0.0;
 #pragma unroll 2
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n >= g.n) break;
     double2 q = normal12(g, ph, n, mu2, ld);
@@ -1480,13 +1485,15 @@ __global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restric
 
 
 // x = 0, r = b; partial of |b|^2.
+template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restrict__ sys, LaunchList L) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   (void)sc;
   const Vec<double2> b(d->vec[S_B]), x(d->vec[S_X]), r(d->vec[S_R]);
   double acc = 0.0;
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
       const double2 v = b[n];
@@ -1500,14 +1507,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restri
 }
 
 // partials of <v_i, w> = sum conj(v_i) w, i < cnt (re, im interleaved).
+template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__ sys, LaunchList L, int s_w,
                                                      int s_v0, int cnt) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   (void)sc;
   const Vec<double2> w(d->vec[s_w]);
-  double2 wv[kSitesPerThread];
+  double2 wv[SPT];
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     wv[m] = cz<double2>();
     if (n < g.n) wv[m] = w[n];
@@ -1517,7 +1526,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__
     const Vec<double2> v(d->vec[s_v0 + q]);
     double ar = 0.0, ai = 0.0;
 #pragma unroll
-    for (int m = 0; m < kSitesPerThread; ++m) {
+    for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
       if (n < g.n) {
         const double2 vv = v[n];
@@ -1537,13 +1546,15 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__
 }
 
 // w -= sum_i h_i v_i, h_i = red[h_off + 2i] + i red[h_off + 2i + 1]; partial of |w|^2.
+template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys, LaunchList L, int s_w, int s_v0,
                                                 int cnt, int h_off) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   const Vec<double2> w(d->vec[s_w]);
-  double2 wv[kSitesPerThread];
+  double2 wv[SPT];
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     wv[m] = cz<double2>();
     if (n < g.n) wv[m] = w[n];
@@ -1552,7 +1563,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
     const double hr = sc->red[h_off + 2 * q], hi = sc->red[h_off + 2 * q + 1];
     const Vec<double2> v(d->vec[s_v0 + q]);
 #pragma unroll
-    for (int m = 0; m < kSitesPerThread; ++m) {
+    for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
       if (n < g.n) {
         const double2 vv = v[n];
@@ -1563,7 +1574,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
   }
   double acc = 0.0;
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
       w.set(n, wv[m]);
@@ -1578,9 +1589,11 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
 // single-precision CG starts on v: r32 = c64(v), z = 0, partial of |r32|^2 (FP32
 // sums).  With pi = 0 there is no preconditioning: z = c64(v).  The z slot of
 // system k is pj[k].
+template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict__ sys, LaunchList L, int s_src,
                                                        int s_v) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   (void)sc;
   const double scale = L.pa[kk];
   const int maxit = L.pi[kk];
@@ -1589,7 +1602,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict
   const Vec<float2> z(d->vec[L.pj[kk]]), r32(d->vec[S_R32]);
   float acc = 0.0f;
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
       double2 a = src[n];
@@ -1638,13 +1651,15 @@ __global__ __launch_bounds__(kBlock) void k_finish(const SysDesc* __restrict__ s
 }
 
 // x = (set ? 0 : x) + sum_{i < cnt} y_i z_i, y from sc->y, z_i the C64 slot S_Z0 + i.
+template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ sys, LaunchList L, int cnt,
                                                     int set) {
-  HUB_PROLOGUE
+  constexpr int TILE = kBlock * SPT;
+  HUB_PROLOGUE_T(TILE)
   const Vec<double2> x(d->vec[S_X]);
-  double2 xv[kSitesPerThread];
+  double2 xv[SPT];
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     xv[m] = cz<double2>();
     if (n < g.n && !set) xv[m] = x[n];
@@ -1653,7 +1668,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
     const double yr = sc->y[2 * q], yi = sc->y[2 * q + 1];
     const Vec<float2> z(d->vec[S_Z0 + q]);
 #pragma unroll
-    for (int m = 0; m < kSitesPerThread; ++m) {
+    for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
       if (n < g.n) {
         const float2 zf = z[n];
@@ -1664,7 +1679,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
     }
   }
 #pragma unroll
-  for (int m = 0; m < kSitesPerThread; ++m) {
+  for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) x.set(n, xv[m]);
   }
@@ -1778,44 +1793,57 @@ static CgList<N> cg_list(const LaunchList& L) {
 }
 
 // One CG stage (1 or 2) over the list; with events, the launch records its own start and end.
-template <typename R, typename LL>
+template <typename R, int SPT, typename LL>
 static void cg_stage(const SysDesc* sys, const LL& c, int stage, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid(c.total_tiles), block(kBlock);
   const bool single = sizeof(R) == 4;
   const int sR = single ? (int)S_R32 : (int)S_R, sP = single ? (int)S_P32 : (int)S_P0,
             sU = single ? (int)S_U32 : (int)S_U;
+  auto kern = stage == 1 ? k_cg1<R, LL, SPT> : k_cg2<R, LL, SPT>;
   if (e0)
-    hipExtLaunchKernelGGL((stage == 1 ? k_cg1<R, LL> : k_cg2<R, LL>), grid, block, 0, st, e0, e1, 0, sys, c, sR, sP,
-                          sU);
+    hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0, e1, 0, sys, c, sR, sP, sU);
   else
-    hipLaunchKernelGGL((stage == 1 ? k_cg1<R, LL> : k_cg2<R, LL>), grid, block, 0, st, sys, c, sR, sP, sU);
+    hipLaunchKernelGGL(kern, grid, block, 0, st, sys, c, sR, sP, sU);
+}
+
+template <typename R, int SPT>
+static void cg_stage_list(const SysDesc* sys, const LaunchList& L, int stage, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
+  if (L.nsys <= kSmallCg)
+    cg_stage<R, SPT>(sys, cg_list<kSmallCg>(L), stage, st, e0, e1);
+  else
+    cg_stage<R, SPT>(sys, cg_list<kMaxSys>(L), stage, st, e0, e1);
 }
 
 template <typename R>
-static void cg_stage_any(const SysDesc* sys, const LaunchList& L, int stage, hipStream_t st, hipEvent_t e0,
-                         hipEvent_t e1) {
-  if (L.nsys <= kSmallCg)
-    cg_stage<R>(sys, cg_list<kSmallCg>(L), stage, st, e0, e1);
+static void cg_stage_any(const SysDesc* sys, const LaunchList& L, int spt, int stage, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1) {
+  if (spt == kSmallSpt)
+    cg_stage_list<R, kSmallSpt>(sys, L, stage, st, e0, e1);
   else
-    cg_stage<R>(sys, cg_list<kMaxSys>(L), stage, st, e0, e1);
+    cg_stage_list<R, kSitesPerThread>(sys, L, stage, st, e0, e1);
 }
 
+static bool spt_ok(const LaunchList& L) { return L.spt == kSmallSpt || L.spt == kSitesPerThread; }
+
 hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st) {
+  if (!spt_ok(L)) return hipErrorInvalidValue;
   for (int stage = 1; stage <= 2; ++stage) {
     if (single)
-      cg_stage_any<float>(sys, L, stage, st, nullptr, nullptr);
+      cg_stage_any<float>(sys, L, L.spt, stage, st, nullptr, nullptr);
     else
-      cg_stage_any<double>(sys, L, stage, st, nullptr, nullptr);
+      cg_stage_any<double>(sys, L, L.spt, stage, st, nullptr, nullptr);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
                            hipEvent_t e0, hipEvent_t e1) {
+  if (!spt_ok(L)) return hipErrorInvalidValue;
   if (single)
-    cg_stage_any<float>(sys, L, stage, st, e0, e1);
+    cg_stage_any<float>(sys, L, L.spt, stage, st, e0, e1);
   else
-    cg_stage_any<double>(sys, L, stage, st, e0, e1);
+    cg_stage_any<double>(sys, L, L.spt, stage, st, e0, e1);
   return hipGetLastError();
 }
 
@@ -1827,20 +1855,31 @@ static hipError_t finish(const SysDesc* sys, const LaunchList& L, int nv, int re
 }
 
 
+// Launch KERNEL<..., SPT> for the tile class of L.
+#define HUB_BY_CLASS(KERNEL, GRID, ...)                                                       \
+  do {                                                                                       \
+    if (L.spt == kSmallSpt)                                                                  \
+      hipLaunchKernelGGL(KERNEL<kSmallSpt>, GRID, dim3(kBlock), 0, st, __VA_ARGS__);          \
+    else                                                                                     \
+      hipLaunchKernelGGL(KERNEL<kSitesPerThread>, GRID, dim3(kBlock), 0, st, __VA_ARGS__);    \
+  } while (0)
+
 hipError_t launch_normal_slot(const SysDesc* sys, const LaunchList& L, int s_in, bool in_c64, int s_b, int s_out,
                               RedMode mode, int red_off, hipStream_t st) {
+  if (!spt_ok(L)) return hipErrorInvalidValue;
   const dim3 grid(L.total_tiles), block(kBlock);
-  if (in_c64)
-    hipLaunchKernelGGL(k_normal_slot<float2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
-  else
-    hipLaunchKernelGGL(k_normal_slot<double2>, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
+  const bool small = L.spt == kSmallSpt;
+  auto kern = in_c64 ? (small ? k_normal_slot<float2, kSmallSpt> : k_normal_slot<float2, kSitesPerThread>)
+                     : (small ? k_normal_slot<double2, kSmallSpt> : k_normal_slot<double2, kSitesPerThread>);
+  hipLaunchKernelGGL(kern, grid, block, 0, st, sys, L, s_in, s_b, s_out, (int)mode);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || mode == RED_NONE) return e;
   return finish(sys, L, 1, red_off, mode, st);
 }
 
 hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, RedMode mode, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_init_zero, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L);
+  if (!spt_ok(L)) return hipErrorInvalidValue;
+  HUB_BY_CLASS(k_cg_init_zero, dim3(L.total_tiles), sys, L);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish(sys, L, 1, 0, mode, st);
@@ -1848,7 +1887,8 @@ hipError_t launch_cg_init_zero(const SysDesc* sys, const LaunchList& L, RedMode 
 
 hipError_t launch_multidot(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int red_off,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_multidot, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt);
+  if (!spt_ok(L)) return hipErrorInvalidValue;
+  HUB_BY_CLASS(k_multidot, dim3(L.total_tiles), sys, L, s_w, s_v0, cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish(sys, L, 2 * cnt, red_off, RED_STORE, st);
@@ -1856,14 +1896,16 @@ hipError_t launch_multidot(const SysDesc* sys, const LaunchList& L, int s_w, int
 
 hipError_t launch_cgs(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0, int cnt, int h_off, int red_off,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_cgs, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_w, s_v0, cnt, h_off);
+  if (!spt_ok(L)) return hipErrorInvalidValue;
+  HUB_BY_CLASS(k_cgs, dim3(L.total_tiles), sys, L, s_w, s_v0, cnt, h_off);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return finish(sys, L, 1, red_off, RED_STORE, st);
 }
 
 hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src, int s_v, hipStream_t st) {
-  hipLaunchKernelGGL(k_prep_inner, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, s_src, s_v);
+  if (!spt_ok(L)) return hipErrorInvalidValue;
+  HUB_BY_CLASS(k_prep_inner, dim3(L.total_tiles), sys, L, s_src, s_v);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // only systems that start a single-precision CG (pi > 0) are finalised
@@ -1883,7 +1925,8 @@ hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src,
 }
 
 hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, int cnt, bool set, hipStream_t st) {
-  hipLaunchKernelGGL(k_xupdate, dim3(L.total_tiles), dim3(kBlock), 0, st, sys, L, cnt, set ? 1 : 0);
+  if (!spt_ok(L)) return hipErrorInvalidValue;
+  HUB_BY_CLASS(k_xupdate, dim3(L.total_tiles), sys, L, cnt, set ? 1 : 0);
   return hipGetLastError();
 }
 
