@@ -122,3 +122,38 @@ def test_request_over_budget_is_busy():
         assert e.value.status == hb.HUB_ERR_BUSY
     finally:
         small.close()
+
+
+@pytest.mark.parametrize("solver", ["fgmres", "cg"])
+def test_mixed_tile_classes_alone_vs_mix(hub, solver):
+    """A system large enough for 2048-site tiles (80x80x48 = 614,400 sites) served together
+    with small ones (1024-site tiles): every CG block then launches both tile classes; each
+    result is bit-identical to the request served alone and meets the oracle's residual."""
+    rng = np.random.default_rng(31)
+    reqs = []
+    for (L, Nt, kt, mu2) in ((80, 48, 0.25, 0.1), (6, 16, 0.25, 0.0), (12, 8, 0.5, 0.05), (24, 16, 0.25, 0.5)):
+        hl = hb.lattice(L, L, Nt, kt)
+        ol = oracle.Lattice(L, L, Nt, kt)
+        phi = rng.normal(0.0, np.sqrt(0.7), size=ol.shape)
+        eta = rng.standard_normal(ol.shape) + 1j * rng.standard_normal(ol.shape)
+        reqs.append((mu2, hl, ol, phi, oracle.apply_Mdag(ol, phi, eta)))
+    opts = hb.default_opts(solver=solver, tol=1e-10)
+
+    def submit(rs):
+        return [hb.hub_submit(hub, hl, mu2, dev(phi), dev(chi[None]), opts=opts) for (mu2, hl, ol, phi, chi) in rs]
+
+    alone = []
+    for r in reqs:
+        p = submit([r])
+        info = _wait(hub, p)[0]
+        alone.append((host(p[0].x).copy(), p[0].S, info))
+    mix = submit(reqs)
+    infos = _wait(hub, mix)
+    for k, (r, p, info) in enumerate(zip(reqs, mix, infos)):
+        mu2, hl, ol, phi, chi = r
+        xa, Sa, ia = alone[k]
+        assert info["converged"] == 1 and ia["converged"] == 1
+        x = host(p.x)
+        assert np.array_equal(x, xa), k
+        assert p.S == Sa, k
+        assert oracle.true_rel_residual(ol, phi, mu2, chi, x.reshape(chi.shape)) <= 1e-10, k
