@@ -86,20 +86,27 @@ namespace api {
 class Server {
  public:
   explicit Server(hub_ctx* ctx) : ctx_(ctx) {
-    hipSetDevice(ctx->device);
-    hipStreamCreateWithFlags(&st_, hipStreamNonBlocking);
+    if (hipSetDevice(ctx->device) != hipSuccess || hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) != hipSuccess) {
+      st_ = nullptr;
+      return;
+    }
     engine_.reset(new Engine(ctx->pool.get(), st_));
+    if (!engine_->ok()) return;
     thread_ = std::thread([this] { run(); });
   }
+  // False if the stream, the engine or the thread could not be set up.
+  bool ok() const { return thread_.joinable(); }
   ~Server() {
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      stop_ = true;
+    if (thread_.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+      }
+      cv_.notify_all();
+      thread_.join();
     }
-    cv_.notify_all();
-    thread_.join();
     engine_.reset();
-    hipStreamDestroy(st_);
+    if (st_) (void)hipStreamDestroy(st_);
   }
 
   hub_status submit(const hub_request& r, uint64_t* ticket) {
@@ -139,7 +146,7 @@ class Server {
 
  private:
   void run() {
-    hipSetDevice(ctx_->device);
+    (void)hipSetDevice(ctx_->device);  // set successfully by the constructor on this device
     for (;;) {
       std::vector<uint64_t> admit;
       {
@@ -224,10 +231,15 @@ class Server {
 Engine* engine_for(hub_ctx* ctx, hipStream_t st) {
   auto it = ctx->engines.find(st);
   if (it != ctx->engines.end()) return it->second.get();
-  Engine* e = new Engine(ctx->pool.get(), st);
+  std::unique_ptr<Engine> e(new Engine(ctx->pool.get(), st));
+  if (!e->ok()) {
+    set_error("could not allocate the solver engine's buffers");
+    return nullptr;
+  }
   e->set_profiling(ctx->profiling);
-  ctx->engines[st].reset(e);
-  return e;
+  Engine* p = e.get();
+  ctx->engines[st] = std::move(e);
+  return p;
 }
 
 }  // namespace api
@@ -270,7 +282,7 @@ hub_status hub_create(hub_ctx** ctx, int device, size_t hbm_budget_bytes) {
 
 hub_status hub_destroy(hub_ctx* ctx) {
   if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   {
     std::lock_guard<std::mutex> lk(ctx->server_mu);
     ctx->server.reset();
@@ -343,6 +355,7 @@ namespace api {
 
 hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_opts& o, hipStream_t stream) {
   Engine* eng = engine_for(ctx, stream);
+  if (!eng) return HUB_ERR_OOM;
   // the phase e^{i phi} once per distinct phi (complex64 too for the mixed solver)
   const bool want32 = o.solver == HUB_FGMRES_MIXED;
   std::map<const double*, std::pair<double2*, float*>> phase;
@@ -507,7 +520,11 @@ hub_status hub_submit(hub_ctx* ctx, const hub_request* req, uint64_t* ticket) {
   Server* srv;
   {
     std::lock_guard<std::mutex> lk(ctx->server_mu);
-    if (!ctx->server) ctx->server.reset(new Server(ctx));
+    if (!ctx->server) {
+      std::unique_ptr<Server> sv(new Server(ctx));
+      if (!sv->ok()) return fail(HUB_ERR_HIP, "could not start the serving stream and engine");
+      ctx->server = std::move(sv);
+    }
     srv = ctx->server.get();
   }
   return srv->submit(*req, ticket);

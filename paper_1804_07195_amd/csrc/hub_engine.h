@@ -93,6 +93,8 @@ class Engine {
  public:
   Engine(Pool* pool, hipStream_t st);
   ~Engine();
+  // False if the engine's own device or pinned buffers could not be allocated.
+  bool ok() const { return ok_; }
   // Allocate workspace and join; false (with the error set) if over budget or full.
   bool add(System* s);
   // Remove a finished system and return its workspace to the pool.
@@ -146,6 +148,7 @@ class Engine {
 
   Pool* pool_;
   hipStream_t st_;
+  bool ok_ = false;
   SysDesc* d_desc_ = nullptr;
   Scal* d_scal_ = nullptr;
   Scal* h_scal_ = nullptr;      // pinned mirror

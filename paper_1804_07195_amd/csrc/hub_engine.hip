@@ -52,13 +52,15 @@ size_t Pool::rounded(size_t bytes) {
 Pool::Pool(int device, size_t budget) : device_(device), budget_(budget) {}
 
 Pool::~Pool() {
-  hipSetDevice(device_);
+  (void)hipSetDevice(device_);
   for (auto& b : free_) {
-    hipEventSynchronize(b.ev);
-    hipEventDestroy(b.ev);
-    hipFree(b.p);
+    if (b.ev) {
+      (void)hipEventSynchronize(b.ev);
+      (void)hipEventDestroy(b.ev);
+    }
+    (void)hipFree(b.p);
   }
-  for (auto& l : live_) hipFree(l.first);
+  for (auto& l : live_) (void)hipFree(l.first);
 }
 
 size_t Pool::in_use() const {
@@ -78,9 +80,9 @@ void* Pool::alloc(size_t bytes, hipStream_t st) {
   for (size_t k = 0; k < free_.size(); ++k) {
     Block& b = free_[k];
     if (b.bytes != sz) continue;
-    if (b.st != st && hipEventQuery(b.ev) != hipSuccess) continue;
+    if (b.st != st && b.ev && hipEventQuery(b.ev) != hipSuccess) continue;
     void* p = b.p;
-    hipEventDestroy(b.ev);
+    if (b.ev) (void)hipEventDestroy(b.ev);
     free_.erase(free_.begin() + (long)k);
     live_.emplace_back(p, sz);
     used_ += sz;
@@ -90,9 +92,11 @@ void* Pool::alloc(size_t bytes, hipStream_t st) {
   while (reserved_ + sz > budget_ && !free_.empty()) {
     Block b = free_.back();
     free_.pop_back();
-    hipEventSynchronize(b.ev);
-    hipEventDestroy(b.ev);
-    hipFree(b.p);
+    if (b.ev) {
+      (void)hipEventSynchronize(b.ev);
+      (void)hipEventDestroy(b.ev);
+    }
+    (void)hipFree(b.p);
     reserved_ -= b.bytes;
   }
   if (reserved_ + sz > budget_) {
@@ -102,7 +106,7 @@ void* Pool::alloc(size_t bytes, hipStream_t st) {
   }
   void* p = nullptr;
   if (hipMalloc(&p, sz) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     set_error("hipMalloc of " + std::to_string(sz) + " bytes failed");
     return nullptr;
   }
@@ -120,8 +124,12 @@ void Pool::release(void* p, hipStream_t st) {
     Block b{p, live_[k].second, st, nullptr};
     live_.erase(live_.begin() + (long)k);
     used_ -= b.bytes;
-    hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
-    hipEventRecord(b.ev, st);
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(b.ev, st) != hipSuccess) {
+      // no event to order later users after the stream's work: wait for it here
+      if (b.ev) (void)hipEventDestroy(b.ev);
+      b.ev = nullptr;
+      (void)hipStreamSynchronize(st);
+    }
     free_.push_back(b);
     return;
   }
@@ -192,12 +200,12 @@ enum Phase : int {
   } while (0)
 
 Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSys, nullptr) {
-  hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys);
-  hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys);
-  hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault);
-  hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4, hipHostMallocDefault);
-  hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_);
-  std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
+  ok_ = hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys) == hipSuccess &&
+        hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys) == hipSuccess &&
+        hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4, hipHostMallocDefault) == hipSuccess &&
+        hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_) == hipSuccess;
+  if (ok_) std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
 }
 
 void Engine::set_profiling(bool on) {
@@ -207,17 +215,17 @@ void Engine::set_profiling(bool on) {
 }
 
 Engine::~Engine() {
-  hipStreamSynchronize(st_);
-  for (hipEvent_t e : events_) hipEventDestroy(e);
+  (void)hipStreamSynchronize(st_);
+  for (hipEvent_t e : events_) (void)hipEventDestroy(e);
   for (System* s : slots_)
     if (s) remove(s);
-  hipFree(d_desc_);
-  hipFree(d_scal_);
-  hipHostFree(h_scal_);
-  hipHostFree(h_flags_);
+  if (d_desc_) (void)hipFree(d_desc_);
+  if (d_scal_) (void)hipFree(d_scal_);
+  if (h_scal_) (void)hipHostFree(h_scal_);
+  if (h_flags_) (void)hipHostFree(h_flags_);
   for (auto& q : inflight_)
     for (auto& b : q)
-      if (b.done) hipEventDestroy(b.done);
+      if (b.done) (void)hipEventDestroy(b.done);
 }
 
 bool Engine::idle() const {
@@ -346,7 +354,8 @@ void Engine::remove(System* s) {
     for (auto& b : q)
       for (System* x : b.v) refs = refs || x == s;
     if (!refs) continue;
-    for (auto& b : q) finish_block(b);
+    // an error here surfaces again at the next synchronising call of the stream
+    for (auto& b : q) (void)finish_block(b);
     q.clear();
   }
   if (s->slot >= 0 && slots_[s->slot] == s) slots_[s->slot] = nullptr;
@@ -745,7 +754,7 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
 // Wait for a block's flags and move the systems that stopped iterating on.
 hipError_t Engine::finish_block(Block& b) {
   const hipError_t w = hipEventSynchronize(b.done);
-  hipEventDestroy(b.done);
+  (void)hipEventDestroy(b.done);
   b.done = nullptr;
   HUB_TRY(w);
   const bool single = b.single;

@@ -86,8 +86,6 @@ __device__ __forceinline__ void cis64(double x, double& c, double& s) {
   s = (k == 0) ? sr : (k == 1) ? cr : (k == 2) ? -sr : -cr;
 }
 
-__device__ __forceinline__ void phase_cs(double ph, double& c, double& s) { cis64(ph, c, s); }
-__device__ __forceinline__ void phase_cs(float ph, float& c, float& s) { sincosf(ph, &s, &c); }
 
 // Workgroups are dispatched round-robin over the XCDs; give XCD x the x-th
 // contiguous chunk of logical tiles.
@@ -199,8 +197,8 @@ __device__ __forceinline__ void cis32(float x, float& c, float& s) {
 }
 
 // The phase e^{i phi} a stencil needs, from one of three sources:
-//  * AnglePhi - phi itself; cos and sin are computed per site (the public operator
-//               kernels, whose input is phi);
+//  * AnglePhi - phi itself (FP64); cos and sin from cis64 per site (the public
+//               operator kernels, whose input is phi);
 //  * PhasePhi - (cos phi, sin phi) precomputed once per solve (the FP64 solver
 //               kernels: a 16-byte load replaces a sincos per site);
 //  * Angle32  - phi reduced to [-pi, pi] and rounded to float once per solve, cos and
@@ -208,15 +206,13 @@ __device__ __forceinline__ void cis32(float x, float& c, float& s) {
 //               FMAs, against 8 bytes for a precomputed complex64 phase).
 // load(k) returns the raw value of site k, cs() turns it into (cos, sin); load2 / cs2
 // do the same for the two sites k, k+1 (k even) of the complex64 pair path.
-template <typename R> struct AnglePhi {
-  Real<R> a;
-  using Raw = R;
-  using Raw2 = hub_f2v;
+template <typename R> struct AnglePhi;
+template <> struct AnglePhi<double> {
+  Real<double> a;
+  using Raw = double;
   __device__ __forceinline__ explicit AnglePhi(const void* q) : a(q) {}
   __device__ __forceinline__ Raw load(int k) const { return a[k]; }
-  __device__ __forceinline__ void cs(Raw v, R& c, R& s) const { phase_cs(v, c, s); }
-  __device__ __forceinline__ Raw2 load2(int k) const { return a.pair(k); }
-  __device__ __forceinline__ void cs2(Raw2 v, int h, float& c, float& s) const { phase_cs(h ? v.y : v.x, c, s); }
+  __device__ __forceinline__ void cs(Raw v, double& c, double& s) const { cis64(v, c, s); }
 };
 struct Angle32 {
   Real<float> a;
