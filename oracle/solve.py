@@ -111,7 +111,8 @@ def _spcg_c64(A32, mu2, v: np.ndarray, tol: float, maxiter: int):
 
 
 def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int = 10, a: float = 5.0,
-                  inner_floor: float = 1e-5, inner_maxiter: int = 5000, max_outer: int = 50):
+                  inner_floor: float = 1e-5, inner_maxiter: int = 5000, max_outer: int = 50,
+                  record: list | None = None):
     """Flexible GMRES of Appendix A with spCG preconditioning, read as follows.
 
     * The initial spCG and every inner spCG start from zero and stop at the relative
@@ -124,7 +125,9 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
     * Outer test: recomputed FP64 true residual |b - A x| <= TOL |b|.
 
     Returns (x, info) with info = dict(outer=number of restart cycles,
-    arnoldi=Arnoldi steps, inner_solves, inner_iters, true_rel_resid)."""
+    arnoldi=Arnoldi steps, inner_solves, inner_iters, true_rel_resid).  A list passed
+    as `record` receives, per restart cycle, the cycle's start x0 and its vectors v_j
+    and z_j (for tests of the cycle's minimal-residual property)."""
     M = build_M(lat, phi)
     A = NormalOperator(lat, phi, mu2, M=M)
     M32 = M.astype(np.complex64)
@@ -178,6 +181,8 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
         rhs = np.zeros(k + 1, dtype=np.complex128)
         rhs[0] = rnorm
         y = np.linalg.lstsq(H[: k + 1, :k], rhs, rcond=None)[0]
+        if record is not None:
+            record.append(dict(x0=x.copy(), V=[v.copy() for v in V[:k]], Z=[z.copy() for z in Z[:k]]))
         for i in range(k):
             x = x + y[i] * Z[i]
         r = bf - A(x)

@@ -4,6 +4,9 @@
   3 kappa and kappa, with an O(delta^2) time-discretisation error of the fitted
   energy (halving delta quarters it), and approach the exact free thermal correlator
   of the ED oracle;
+* time translation: on a field rolled by s slices the correlator from source slice
+  s equals the one from slice 0 on the original field at every separation, the
+  separations that wrap the antiperiodic boundary included;
 * the exponential fit returns E exactly for a pure exponential.
 """
 import numpy as np
@@ -46,3 +49,13 @@ def test_free_correlator_approaches_ed():
 def test_fit_of_a_pure_exponential():
     tau = np.arange(64) * 0.125
     assert abs(oc.fit_energy(2.5 * np.exp(-1.7 * tau), 0.125, (0.2, 1.0)) - 1.7) < 1e-12
+
+
+def test_time_translation_with_the_antiperiodic_wrap():
+    lat = Lattice(2, 1, 16, 0.5)
+    phi = np.random.default_rng(3).normal(0.0, 0.8, size=lat.shape)
+    for v in (oc.GAMMA, oc.M_POINT):
+        ref = oc.propagator_correlator(lat, phi, v, t0s=[0])
+        for s in (3, 8, 13):
+            got = oc.propagator_correlator(lat, np.roll(phi, s, axis=0), v, t0s=[s])
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)

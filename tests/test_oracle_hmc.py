@@ -192,3 +192,5 @@ def test_metropolis_decision_and_rejection():
     p_rej, acc2, dH2, _, _, _ = hmc.hmc_update(lat, U_t, phi, pi, rho, mts, [1, 1], 4, u=math.exp(-dH) * 1.0001,
                                                t=0.5)
     assert not acc2 and np.array_equal(p_rej, phi) and dH2 == dH
+    _, acc3, dH3, _, _, _ = hmc.hmc_update(lat, U_t, phi, pi, rho, mts, [1, 1], 4, u=math.exp(-dH) * 0.9999, t=0.5)
+    assert acc3 and dH3 == dH

@@ -10,8 +10,11 @@ that reduces to a library routine, brute force, or a number the paper prints:
 * gauge covariance M[phi'] = D M[phi] D^dagger for time-dependent phases;
 * Sec. 3: M M^dagger Hermitian positive definite (and != M^dagger M);
 * solve: CG vs LU vs eigendecomposition; chi = M rho gives M^dagger x = rho;
+* CG iterates: the k-th iterate is the Galerkin solution on the Krylov space
+  K_k(A, b), and the complex64 inner CG follows the FP64 one to single precision;
 * eqs. (p_dot), (eta_xi): force vs cancellation-free central differences;
-* Algorithm A.1 method oracle reaches the requested true residual;
+* Algorithm A.1 method oracle reaches the requested true residual, and without
+  inner solves one cycle of it is GMRES(m): the minimal residual over K_m(A, b);
 * Sec. 6.1: the non-interacting largest eigenvalue sits inside the paper's fit.
 """
 import math
@@ -237,6 +240,49 @@ def test_heatbath_source_gives_xi_equal_rho():
     assert math.isclose(S, np.vdot(rho[0], rho[0]).real, rel_tol=1e-11)
 
 
+def _krylov_basis(Ad, b, k):
+    """Orthonormal basis of span{b, A b, ..., A^{k-1} b} from the normalised power
+    sequence and a QR factorisation (no Arnoldi recurrence)."""
+    K = [b / np.linalg.norm(b)]
+    for _ in range(k - 1):
+        v = Ad @ K[-1]
+        K.append(v / np.linalg.norm(v))
+    return np.linalg.qr(np.stack(K, axis=1))[0]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_cg_iterate_is_the_krylov_galerkin_solution(k):
+    """From x0 = 0 the k-th CG iterate minimises the A-norm of the error over
+    K_k(A, b): x_k = V (V^H A V)^{-1} V^H b for an orthonormal basis V of K_k."""
+    lat = Lattice(3, 3, 8, 0.5)
+    rng = np.random.default_rng(7)
+    A = NormalOperator(lat, rand_phi(rng, lat), 0.05)
+    Ad = A.dense()
+    b = rand_c(rng, lat.n)
+    V = _krylov_basis(Ad, b, k)
+    want = V @ np.linalg.solve(V.conj().T @ Ad @ V, V.conj().T @ b)
+    x, its, _ = oracle.cg(A, b, tol=0.0, maxiter=k)
+    assert its == k
+    assert np.linalg.norm(x - want) <= 1e-10 * np.linalg.norm(want)
+
+
+def test_complex64_inner_cg_follows_the_fp64_cg():
+    """The inner CG of Algorithm A.1 is the same recurrence in complex64: its first
+    iterates agree with the FP64 CG's to single precision."""
+    from oracle.solve import _spcg_c64
+    lat = Lattice(3, 3, 8, 0.5)
+    rng = np.random.default_rng(17)
+    A = NormalOperator(lat, rand_phi(rng, lat), 0.05)
+    A32 = lambda v: (A.M.astype(np.complex64) @ (A.Mh.astype(np.complex64) @ v)
+                     + np.float32(0.05) * v)
+    b = rand_c(rng, lat.n)
+    for k in (1, 2, 4, 6):
+        z, its = _spcg_c64(A32, 0.05, b, 0.0, k)
+        x, _, _ = oracle.cg(A, b, tol=0.0, maxiter=k)
+        assert its == k and z.dtype == np.complex64
+        assert np.linalg.norm(z - x) <= 1e-5 * np.linalg.norm(x)
+
+
 def _fd_force(lat, phi, mu2, chi, k, h):
     """Central difference of S in phi_k, cancellation free:
     S(+) - S(-) = x+^dagger (A- - A+) x-, x+- = A+-^{-1} chi."""
@@ -304,6 +350,47 @@ def test_alg_a1_method_oracle_reaches_tolerance(mu2):
     xref, _ = oracle.solve(lat, phi, mu2, chi, tol=1e-13)
     assert np.linalg.norm((x - xref).ravel()) <= 1e-6 * np.linalg.norm(xref.ravel())
     assert info["inner_solves"] >= 2
+
+
+def test_alg_a1_without_inner_solves_is_gmres():
+    """With a = 1e25 the test TOL a |b| / ERR < 1 never holds (z_j = v_j) and the
+    initial spCG stops before its first step (x0 = 0), so one restart cycle of
+    Algorithm A.1 is GMRES(m): x minimises |b - A x| over K_k(A, b), k the number of
+    Arnoldi steps taken."""
+    lat = Lattice(3, 3, 8, 0.5)
+    rng = np.random.default_rng(7)
+    phi = rand_phi(rng, lat)
+    Ad = NormalOperator(lat, phi, 0.05).dense()
+    b = rand_c(rng, lat.n)
+    x, info = oracle.fgmres_alg_a1(lat, phi, 0.05, b, TOL=1e-10, a=1e25, max_outer=1)
+    assert info["outer"] == 1 and info["inner_iters"] == 0 and info["arnoldi"] == 10
+    V = _krylov_basis(Ad, b, info["arnoldi"])
+    want = V @ np.linalg.lstsq(Ad @ V, b, rcond=None)[0]
+    assert np.linalg.norm(x - want) <= 1e-9 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("mu2", [0.0, 0.05])
+def test_alg_a1_cycle_minimises_the_residual_over_the_z_vectors(mu2):
+    """Flexible GMRES: each restart cycle ends at the x in x0 + span{z_1 .. z_k} with
+    the least |b - A x| (the z_j are the spCG outputs), and the v_j are orthonormal.
+    A complex Hessenberg entry with a wrong conjugation or a missing projection
+    breaks this although the restarted solver may still converge."""
+    w = WORKLOADS["tiny"]
+    lat = lat_of(w)
+    phi, eta = draw_inputs(w, batch=1)
+    chi = oracle.apply_Mdag(lat, phi, eta[0]).ravel()
+    Ad = NormalOperator(lat, phi, mu2).dense()
+    cycles = []
+    x, info = oracle.fgmres_alg_a1(lat, phi, mu2, chi, TOL=1e-10, record=cycles)
+    assert info["true_rel_resid"] <= 1e-10 and len(cycles) == info["outer"] >= 1
+    ends = [c["x0"] for c in cycles[1:]] + [x]
+    for c, x1 in zip(cycles, ends):
+        V, Z = np.stack(c["V"], axis=1), np.stack(c["Z"], axis=1)
+        assert np.abs(V.conj().T @ V - np.eye(V.shape[1])).max() <= 1e-8   # classical Gram-Schmidt
+        r0 = chi - Ad @ c["x0"]
+        best = c["x0"] + Z @ np.linalg.lstsq(Ad @ Z, r0, rcond=None)[0]
+        assert np.linalg.norm(chi - Ad @ x1) <= (1 + 1e-6) * np.linalg.norm(chi - Ad @ best) + 1e-14 * np.linalg.norm(chi)
+        assert np.linalg.norm(x1 - best) <= 1e-6 * np.linalg.norm(best)
 
 
 def _read_golden(name):
