@@ -1,0 +1,129 @@
+"""The C ABI at its limits, against the oracle (GPU).
+
+* HUB_MAX_BATCH systems in one call: M, M^dagger and M M^dagger + mu^2 applies, the
+  force, and solves with both solvers (a different shift per system) match the
+  oracle system by system; one system more is refused with HUB_ERR_ARG;
+* the restart lengths m = 1 and m = HUB_MAX_RESTART still reach the tolerance;
+* degenerate lattices (one unit cell, one or two time slices: the bonds and the two
+  temporal hops of a site coincide) solve to the tolerance with both solvers and
+  give the oracle's solution.
+
+Bars as in the other parity tests: applies and force <= 1e-13 relative to
+max(1, max|y|); solves: the oracle's recomputed true residual <= 1e-10 and the
+solution within 1e-6 of the oracle's dense LU solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.operator import NormalOperator, build_M
+from paper_1804_07195_amd import binding as hb
+from tests.gpu_helpers import dev, host, lattices, rel2, rel_max
+
+pytestmark = pytest.mark.gpu
+
+MAXB = 64  # HUB_MAX_BATCH of include/hub.h
+
+
+@pytest.fixture(scope="module")
+def hub():
+    ctx = hb.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def _inputs(ol, batch, seed, scale=0.8):
+    rng = np.random.default_rng(seed)
+    phi = rng.normal(0.0, scale, size=ol.shape)
+    x = rng.standard_normal((batch,) + ol.shape) + 1j * rng.standard_normal((batch,) + ol.shape)
+    return phi, x
+
+
+def test_applies_and_force_at_the_batch_limit(hub):
+    hl, ol = lattices(12, 12, 16, 0.25, 0.05)
+    phi, x = _inputs(ol, MAXB, 1)
+    M = build_M(ol, phi)
+    pd, xd = dev(phi), dev(x)
+    mu2 = [0.01 * k for k in range(MAXB)]
+    y = host(hb.hub_apply_M(hub, hl, pd, xd))
+    yd = host(hb.hub_apply_Mdag(hub, hl, pd, xd))
+    yn = host(hb.hub_apply_normal(hub, hl, pd, mu2, xd))
+    F = host(hb.hub_force(hub, hl, pd, xd))
+    for b in range(MAXB):
+        assert rel_max(y[b], oracle.apply_M(ol, phi, x[b], M=M)) <= 1e-13
+        assert rel_max(yd[b], oracle.apply_Mdag(ol, phi, x[b], M=M)) <= 1e-13
+        want_n = NormalOperator(ol, phi, mu2[b], M=M)(x[b].ravel()).reshape(ol.shape)
+        assert rel_max(yn[b], want_n) <= 1e-13
+        assert rel_max(F[b], oracle.force(ol, phi, x[b])) <= 1e-13
+
+
+def test_one_system_beyond_the_batch_limit_is_refused(hub):
+    hl, ol = lattices(3, 3, 8, 0.5)
+    phi = dev(np.zeros(ol.shape))
+    x = dev(np.ones((MAXB + 1,) + ol.shape, complex))
+    with pytest.raises(hb.HubError):
+        hb.hub_apply_M(hub, hl, phi, x)
+    with pytest.raises(hb.HubError):
+        hb.hub_solve(hub, hl, phi, [0.1] * (MAXB + 1), x)
+    with pytest.raises(hb.HubError):
+        hb.hub_force(hub, hl, phi, x)
+
+
+@pytest.mark.parametrize("solver", ["cg", "fgmres"])
+def test_solve_at_the_batch_limit(hub, solver):
+    hl, ol = lattices(6, 6, 8, 0.5)
+    phi, eta = _inputs(ol, MAXB, 2, scale=1.0)
+    pd = dev(phi)
+    chi = hb.hub_apply_Mdag(hub, hl, pd, dev(eta))
+    ch = host(chi)
+    mu2 = [0.0 if b % 8 == 0 else 0.005 * b for b in range(MAXB)]
+    x, info, st = hb.hub_solve(hub, hl, pd, mu2, chi, opts=hb.default_opts(solver=solver))
+    assert st == hb.HUB_OK
+    xs = host(x)
+    M = build_M(ol, phi)
+    for b in range(MAXB):
+        A = NormalOperator(ol, phi, mu2[b], M=M)
+        assert info[b]["converged"] == 1
+        assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b], A=A) <= 1e-10
+        want = np.linalg.solve(A.dense(), ch[b].ravel())
+        assert rel2(xs[b].ravel(), want) <= 1e-6
+
+
+@pytest.mark.parametrize("m", [1, 20])
+def test_restart_length_limits(hub, m):
+    hl, ol = lattices(12, 12, 16, 0.25)
+    phi, eta = _inputs(ol, 2, 3, scale=0.9)
+    pd = dev(phi)
+    chi = hb.hub_apply_Mdag(hub, hl, pd, dev(eta))
+    ch = host(chi)
+    mu2 = [0.0, 0.05]
+    x, info, st = hb.hub_solve(hub, hl, pd, mu2, chi, opts=hb.default_opts(solver="fgmres", restart_m=m))
+    assert st == hb.HUB_OK
+    xs = host(x)
+    for b in range(2):
+        assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b]) <= 1e-10
+    with pytest.raises(hb.HubError):
+        hb.hub_solve(hub, hl, pd, mu2, chi, opts=hb.default_opts(solver="fgmres", restart_m=21))
+
+
+DEGENERATE = [(1, 1, 1, 0.4, 0.0), (1, 1, 2, 0.4, 0.1), (1, 1, 3, 0.3, 0.0), (2, 1, 1, 0.5, 0.0), (1, 3, 2, 0.2, 0.05)]
+
+
+@pytest.mark.parametrize("shape", DEGENERATE, ids=[f"{a}x{b}x{c}" for a, b, c, _, _ in DEGENERATE])
+@pytest.mark.parametrize("solver", ["cg", "fgmres"])
+def test_degenerate_lattices_solve(hub, shape, solver):
+    hl, ol = lattices(*shape)
+    phi, eta = _inputs(ol, 3, 4, scale=0.7)
+    pd = dev(phi)
+    chi = hb.hub_apply_Mdag(hub, hl, pd, dev(eta))
+    ch = host(chi)
+    mu2 = [0.1, 0.5, 1.0]
+    x, info, st = hb.hub_solve(hub, hl, pd, mu2, chi, opts=hb.default_opts(solver=solver))
+    assert st == hb.HUB_OK
+    xs = host(x)
+    for b in range(3):
+        A = NormalOperator(ol, phi, mu2[b])
+        assert np.all(np.isfinite(xs[b]))
+        assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b], A=A) <= 1e-10
+        want = np.linalg.solve(A.dense(), ch[b].ravel())
+        assert rel2(xs[b].ravel(), want) <= 1e-6
