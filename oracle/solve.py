@@ -126,8 +126,9 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
 
     Returns (x, info) with info = dict(outer=number of restart cycles,
     arnoldi=Arnoldi steps, inner_solves, inner_iters, true_rel_resid).  A list passed
-    as `record` receives, per restart cycle, the cycle's start x0 and its vectors v_j
-    and z_j (for tests of the cycle's minimal-residual property)."""
+    as `record` receives, per restart cycle, the cycle's start x0, its vectors v_j
+    and z_j and the values TOL a |b| / ERR of the inner-solve test (for tests of the
+    cycle's minimal-residual property and of how close that test came to 1)."""
     M = build_M(lat, phi)
     A = NormalOperator(lat, phi, mu2, M=M)
     M32 = M.astype(np.complex64)
@@ -149,7 +150,7 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
     w = r.copy()
     while ERR > TOL * bnorm and info["outer"] < max_outer:
         rnorm = ERR
-        V, Z = [], []
+        V, Z, ratios = [], [], []
         H = np.zeros((m + 1, m), dtype=np.complex128)
         k = 0
         for j in range(m):
@@ -160,6 +161,7 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
                 break
             V.append(w / wn)
             ratio = TOL * a * bnorm / ERR
+            ratios.append(ratio)
             if ratio < 1.0:
                 z, its = _spcg_c64(A32, mu2, V[j], max(ratio, inner_floor), inner_maxiter)
                 info["inner_solves"] += 1
@@ -182,7 +184,8 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
         rhs[0] = rnorm
         y = np.linalg.lstsq(H[: k + 1, :k], rhs, rcond=None)[0]
         if record is not None:
-            record.append(dict(x0=x.copy(), V=[v.copy() for v in V[:k]], Z=[z.copy() for z in Z[:k]]))
+            record.append(dict(x0=x.copy(), V=[v.copy() for v in V[:k]], Z=[z.copy() for z in Z[:k]],
+                               ratio=list(ratios[:k])))
         for i in range(k):
             x = x + y[i] * Z[i]
         r = bf - A(x)

@@ -155,11 +155,15 @@ constexpr int kSmallCg = 4;
 
 // Tile class of a system: sites per thread of all its solver kernels.  Large systems
 // take kSitesPerThread (2048-site tiles: fewer workgroups, fixed costs spread over more
-// sites); a system below kBigSites takes kSmallSpt, so that its grids have enough
-// workgroups to hide latency (the CG stages of a 48x48x64 system run 9-13% faster with
-// 1024-site tiles, those of a 102x102x64 system 7% slower).  Launch lists hold systems
-// of one class.
-constexpr int kSmallSpt = 4;
+// sites); a system below kBigSites takes kSmallSpt (512-site tiles), so that its grids
+// have enough workgroups to hide latency and each thread's serial chain stays short
+// (the CG stages of a 102x102x64 system run 7% slower with 1024-site tiles than with
+// 2048; a 48x48x64 solve is 5-9% faster and a 12x12x32 one 11-21% faster with 512-site
+// tiles than with 1024).  Launch lists hold systems of one class.
+#ifndef HUB_SMALL_SPT
+#define HUB_SMALL_SPT 2
+#endif
+constexpr int kSmallSpt = HUB_SMALL_SPT;
 constexpr int kBigSites = 300 * kTile;
 inline int spt_of(int n) { return n >= kBigSites ? kSitesPerThread : kSmallSpt; }
 inline int tiles_of_spt(int n, int spt) { return (n + kBlock * spt - 1) / (kBlock * spt); }

@@ -127,7 +127,7 @@ def test_request_over_budget_is_busy():
 @pytest.mark.parametrize("solver", ["fgmres", "cg"])
 def test_mixed_tile_classes_alone_vs_mix(hub, solver):
     """A system large enough for 2048-site tiles (80x80x48 = 614,400 sites) served together
-    with small ones (1024-site tiles): every CG block then launches both tile classes; each
+    with small ones (512-site tiles): every CG block then launches both tile classes; each
     result is bit-identical to the request served alone and meets the oracle's residual."""
     rng = np.random.default_rng(31)
     reqs = []
