@@ -5,7 +5,9 @@
 * each request's x, S and dS/dphi are bit-identical when it is served alone and when
   it is served together with the rest of the stream (per-system reductions in a
   fixed order, independent of the batch);
-* S and the force of a served request match the synchronous calls.
+* S and the force of a served request match the synchronous calls;
+* more requests in flight than the engine has system slots (64) queue and are
+  admitted as slots free up; every one of them converges.
 """
 import time
 
@@ -99,6 +101,23 @@ def test_served_outputs_match_synchronous_calls(hub):
         assert torch.equal(F.reshape(p.dS.shape), p.dS)
         Fo = oracle.force(ol, phi, host(p.x).reshape(chi.shape))
         assert np.linalg.norm(host(p.dS) - Fo) <= 1e-8 * np.linalg.norm(Fo)
+
+
+@pytest.mark.parametrize("solver", ["fgmres", "cg"])
+def test_more_requests_than_engine_slots(hub, solver):
+    reqs = _requests(100, seed=23)
+    opts = hb.default_opts(solver=solver)
+    pend = _submit(hub, reqs, opts)
+    infos = _wait(hub, pend, timeout=300.0)
+    for k, (r, p, info) in enumerate(zip(reqs, pend, infos)):
+        w, hl, ol, phi, chi = r
+        assert info["converged"] == 1, k
+        res = oracle.true_rel_residual(ol, phi, w.mu2[0], chi, host(p.x).reshape(chi.shape))
+        assert res <= 1e-10, (k, res)
+    # the last request, admitted late, gives the same bits as when served alone
+    alone = _submit(hub, [reqs[-1]], opts)
+    _wait(hub, alone)
+    assert np.array_equal(host(alone[0].x), host(pend[-1].x))
 
 
 def test_poll_unknown_ticket_and_release(hub):
