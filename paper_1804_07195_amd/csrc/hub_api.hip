@@ -187,7 +187,11 @@ class Server {
         std::lock_guard<std::mutex> lk(mu_);
         for (auto it = back.rbegin(); it != back.rend(); ++it) queue_.push_front(*it);
       }
-      if (engine_->count() == 0) continue;
+      if (engine_->count() == 0) {
+        // nothing runs: a request that did not fit waits for workspace held elsewhere
+        if (!back.empty()) std::this_thread::sleep_for(std::chrono::milliseconds(1));
+        continue;
+      }
       if (engine_->step() != hipSuccess) {
         // a HIP failure: fail every running request
         for (auto& t : running_) {
