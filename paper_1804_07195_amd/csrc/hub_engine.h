@@ -152,6 +152,9 @@ class Engine {
   SysDesc* d_desc_ = nullptr;
   Scal* d_scal_ = nullptr;
   Scal* h_scal_ = nullptr;      // pinned mirror
+  Scal* h_pub_ = nullptr;       // host-coherent copy written by k_publish, followed by its flag
+  unsigned* h_pub_flag_ = nullptr;
+  unsigned pub_seq_ = 0;
   std::vector<System*> slots_;
   bool profiling_ = false;
   std::vector<hipEvent_t> events_;      // pool for kernel timing

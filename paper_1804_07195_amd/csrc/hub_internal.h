@@ -215,6 +215,11 @@ hipError_t launch_md_kick(double* pi, const double* phi, const double* G, double
 // Batched solver kernels over the systems of a LaunchList (descriptors in `sys`).
 // FP64 or C64 CG iteration in two stages (see hub_kernels.hip).
 // The batched solver launchers below take systems of one tile class (L.spt).
+// Copy the Scal records d[0, cnt) to host-coherent memory h[0, cnt), then write seq to
+// *flag (host-coherent) with a system-scope release, so that the host can poll the
+// flag instead of synchronising the stream.  One workgroup.
+static_assert(sizeof(Scal) % 8 == 0, "Scal is copied in 8-byte words");
+hipError_t launch_publish(const Scal* d, Scal* h, int cnt, unsigned* flag, unsigned seq, hipStream_t st);
 hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, hipStream_t st);
 // One stage (1 or 2) of the CG iteration.  With events, the launch records the
 // kernel's own start and end timestamps into them (hipExtLaunchKernel).

@@ -1622,29 +1622,41 @@ __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict
   store_partials(d, tile, &tot, 1);
 }
 
-// One workgroup per system: sum the generic partials (nv values) in a fixed order
-// into red[red_off..]; with RED_CG_SETUP start a CG on rr = result[0]:
-// stop2 = pa + pr*rr, maxit = pi, iters 0, active iff rr > stop2.
-__global__ __launch_bounds__(kBlock) void k_finish(const SysDesc* __restrict__ sys, LaunchList L, int nv,
-                                                   int red_off, int mode) {
-  const int kk = blockIdx.x;
+// One workgroup per system and value (grid nsys x nv): sum the generic partials of
+// value q in a fixed order into red[red_off + q]; with RED_CG_SETUP the q = 0
+// workgroup also starts a CG on rr = result[0]: stop2 = pa + pr*rr, maxit = pi,
+// iters 0, active iff rr > stop2.
+__global__ __launch_bounds__(kBlock) void k_finish(const SysDesc* __restrict__ sys, LaunchList L, int red_off,
+                                                   int mode) {
+  const int kk = blockIdx.x, q = blockIdx.y;
   const SysDesc* __restrict__ d = sys + L.sys[kk];
   Scal* sc = d->sc;
-  for (int q = 0; q < nv; ++q) {
-    const double s = sum_partials(d->part + q, d->ntiles, kMaxRed);
-    if (threadIdx.x == 0) {
-      sc->red[red_off + q] = s;
-      if (q == 0 && mode == RED_CG_SETUP) {
-        const double stop2 = L.pa[kk] + L.pr[kk] * s;
-        sc->rrv[0] = s;
-        sc->stop2 = stop2;
-        sc->maxit = L.pi[kk];
-        sc->iters = 0;
-        store_active(sc, s > stop2 ? 1 : 0);
-      }
+  const double s = sum_partials(d->part + q, d->ntiles, kMaxRed);
+  if (threadIdx.x == 0) {
+    sc->red[red_off + q] = s;
+    if (q == 0 && mode == RED_CG_SETUP) {
+      const double stop2 = L.pa[kk] + L.pr[kk] * s;
+      sc->rrv[0] = s;
+      sc->stop2 = stop2;
+      sc->maxit = L.pi[kk];
+      sc->iters = 0;
+      store_active(sc, s > stop2 ? 1 : 0);
     }
   }
 }
+
+// Scal records to host-coherent memory, every thread's stores made visible at system
+// scope before the barrier, then the flag.
+__global__ __launch_bounds__(kBlock) void k_publish(const Scal* __restrict__ d, Scal* h, int nw, unsigned* flag,
+                                                    unsigned seq) {
+  const unsigned long long* __restrict__ src = reinterpret_cast<const unsigned long long*>(d);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(h);
+  for (int k = threadIdx.x; k < nw; k += kBlock) dst[k] = src[k];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 
 // x = (set ? 0 : x) + sum_{i < cnt} y_i z_i, y from sc->y, z_i the C64 slot S_Z0 + i.
 template <int SPT>
@@ -1844,9 +1856,16 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
 }
 
 
+hipError_t launch_publish(const Scal* d, Scal* h, int cnt, unsigned* flag, unsigned seq, hipStream_t st) {
+  if (cnt < 1 || cnt > kMaxSys || !d || !h || !flag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(kBlock), 0, st, d, h, cnt * (int)(sizeof(Scal) / 8), flag, seq);
+  return hipGetLastError();
+}
+
 static hipError_t finish(const SysDesc* sys, const LaunchList& L, int nv, int red_off, RedMode mode,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_finish, dim3(L.nsys), dim3(kBlock), 0, st, sys, L, nv, red_off, (int)mode);
+  if (nv < 1 || nv > kMaxRed || red_off < 0 || red_off + nv > kMaxRed) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish, dim3(L.nsys, nv), dim3(kBlock), 0, st, sys, L, red_off, (int)mode);
   return hipGetLastError();
 }
 
