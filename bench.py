@@ -25,6 +25,7 @@ usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-serv
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import multiprocessing as mp
@@ -244,40 +245,47 @@ def main():
                 "timed_over": f"{prof_steps} steps after the timed region, HIP events bound to every launch",
                 "alg_bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1))}
 
-    # M-apply bandwidth (FP64, one system): resident and with buffers rotated past the cache
-    def timed(fn, K, stream=None):
+    # M-apply bandwidth (FP64, one system): resident and with buffers rotated past the cache.
+    # The launches go back to back through the C ABI with their arguments marshalled once,
+    # so that the host stays ahead of the GPU (through the checking Python wrapper a call
+    # costs more host time than the kernel, and the loop would time Python); the host time
+    # per call is reported next to the GPU time.
+    lib = hb.load()
+    sh = hb._stream(None)
+    latref = ctypes.byref(hl)
+
+    def timed_raw(args, K):
         s = torch.cuda.Event(enable_timing=True)
         e = torch.cuda.Event(enable_timing=True)
+        bad = 0
         s.record()
-        for _ in range(K):
-            fn()
+        t0 = time.perf_counter()
+        for k in range(K):
+            p, x, y = args[k % len(args)]
+            bad |= lib.hub_apply_M(ctx.handle, latref, p, x, y, 1, sh)
+        host_us = (time.perf_counter() - t0) / K * 1e6
         e.record()
         torch.cuda.synchronize()
-        return s.elapsed_time(e) / K
+        if bad:
+            raise RuntimeError("hub_apply_M failed: " + lib.hub_last_error().decode())
+        return s.elapsed_time(e) / K, host_us
 
     y = torch.empty_like(ed[0:1])
-    for _ in range(5):
-        hb.hub_apply_M(ctx, hl, pd, ed[0:1], y)
-    hot_ms = timed(lambda: hb.hub_apply_M(ctx, hl, pd, ed[0:1], y), 200)
+    hot_args = [(pd.data_ptr(), ed[0:1].data_ptr(), y.data_ptr())]
+    timed_raw(hot_args, 5)
+    hot_ms, hot_host = timed_raw(hot_args, 200)
     nrot = 1 + (2 * MALL_BYTES) // int(w.nsites * APPLY_BYTES)
     xs = [torch.randn_like(ed[0:1]) for _ in range(nrot)]
     ys = [torch.empty_like(ed[0:1]) for _ in range(nrot)]
     ps = [pd.clone() for _ in range(nrot)]
-    cnt = [0]
-
-    def cold():
-        k = cnt[0] % nrot
-        cnt[0] += 1
-        hb.hub_apply_M(ctx, hl, ps[k], xs[k], ys[k])
-
-    for _ in range(nrot):
-        cold()
-    cold_ms = timed(cold, 10 * nrot)
+    cold_args = [(ps[k].data_ptr(), xs[k].data_ptr(), ys[k].data_ptr()) for k in range(nrot)]
+    timed_raw(cold_args, nrot)
+    cold_ms, cold_host = timed_raw(cold_args, 20 * nrot)
     apply_bytes = w.nsites * APPLY_BYTES
     m_apply = {"kernel": "k_apply<M>", "alg_bytes": int(apply_bytes),
                "hot_us": round(1e3 * hot_ms, 3), "hot_GBps": round(apply_bytes / (hot_ms * 1e-3) / 1e9, 1),
                "cold_us": round(1e3 * cold_ms, 3), "cold_GBps": round(apply_bytes / (cold_ms * 1e-3) / 1e9, 1),
-               "cold_buffers": nrot}
+               "cold_buffers": nrot, "host_us_per_call": [round(hot_host, 2), round(cold_host, 2)]}
     del xs, ys, ps
 
     # FP64 CG on the same systems, same accuracy
