@@ -111,3 +111,32 @@ def test_create_without_device_reports_hip_error(lib):
     h = ctypes.c_void_p()
     assert lib.hub_create(ctypes.byref(h), 0, 0) == b.HUB_ERR_HIP
     assert len(lib.hub_last_error()) > 0
+
+
+def test_header_is_plain_c(lib, tmp_path):
+    """include/hub.h compiles as C99 next to the HIP runtime header, and a C program
+    that takes the address of every declared entry point links against libhub.so and
+    runs its host-only call (no device is touched)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    names = declared_functions()
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include "hub.h"\n#include <stdio.h>\n'
+        "int main(void) {\n"
+        "  void* fns[] = {" + ", ".join(f"(void*){n}" for n in names) + "};\n"
+        "  hub_solve_opts o;\n  hub_default_opts(&o);\n"
+        '  printf("%d %d %d\\n", (int)(sizeof(fns) / sizeof(fns[0])), o.restart_m, fns[0] != 0);\n'
+        "  return 0;\n}\n")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                        "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include", str(src), "-o", str(exe),
+                        "-L" + libdir, "-lhub", "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == [str(len(names)), "10", "1"]
