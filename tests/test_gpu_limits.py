@@ -6,7 +6,9 @@
 * the restart lengths m = 1 and m = HUB_MAX_RESTART still reach the tolerance;
 * degenerate lattices (one unit cell, one or two time slices: the bonds and the two
   temporal hops of a site coincide) solve to the tolerance with both solvers and
-  give the oracle's solution.
+  give the oracle's solution;
+* a batch of zero systems and a zero lattice extent are refused by the C ABI, and a
+  zero right-hand side gives x = 0 without iterating.
 
 Bars as in the other parity tests: applies and force <= 1e-13 relative to
 max(1, max|y|); solves: the oracle's recomputed true residual <= 1e-10 and the
@@ -14,6 +16,7 @@ solution within 1e-6 of the oracle's dense LU solution.
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from oracle.operator import NormalOperator, build_M
@@ -127,3 +130,33 @@ def test_degenerate_lattices_solve(hub, shape, solver):
         assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b], A=A) <= 1e-10
         want = np.linalg.solve(A.dense(), ch[b].ravel())
         assert rel2(xs[b].ravel(), want) <= 1e-6
+
+
+def test_empty_and_zero_inputs(hub):
+    """A batch of zero systems and a lattice with a zero extent are refused by the C ABI
+    itself (HUB_ERR_ARG) before anything is enqueued; an all-zero right-hand side solves
+    to x = 0 without iterating."""
+    import ctypes
+    lib = hb.load()
+    hl, ol = lattices(3, 3, 8, 0.5)
+    phi = dev(np.zeros(ol.shape))
+    x = dev(np.ones((1,) + ol.shape, complex))
+    y = torch.empty_like(x)
+    for batch in (0, -1):
+        assert lib.hub_apply_M(hub.handle, ctypes.byref(hl), phi.data_ptr(), x.data_ptr(), y.data_ptr(), batch,
+                               None) == hb.HUB_ERR_ARG
+        o = hb.default_opts()
+        info = (hb.HubSolveInfo * 1)()
+        mu = (ctypes.c_double * 1)(0.1)
+        assert lib.hub_solve(hub.handle, ctypes.byref(hl), phi.data_ptr(), mu, batch, x.data_ptr(), y.data_ptr(),
+                             ctypes.byref(o), info, None) == hb.HUB_ERR_ARG
+    flat = hb.lattice(3, 3, 8, 0.5)
+    flat.Nt = 0
+    assert lib.hub_apply_M(hub.handle, ctypes.byref(flat), phi.data_ptr(), x.data_ptr(), y.data_ptr(), 1,
+                           None) == hb.HUB_ERR_ARG
+    for solver in ("cg", "fgmres"):
+        z = dev(np.zeros((2,) + ol.shape, complex))
+        xs, infos, st = hb.hub_solve(hub, hl, dev(np.random.default_rng(1).normal(size=ol.shape)), [0.0, 0.3], z,
+                                     opts=hb.default_opts(solver=solver))
+        assert st == hb.HUB_OK and torch.count_nonzero(xs) == 0
+        assert all(i["converged"] == 1 and i["inner_iters"] == 0 for i in infos)
