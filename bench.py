@@ -117,8 +117,11 @@ def _oracle_worker(args):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cg2_c64_102x102x64.md")
+# the kernels, and what decides the mix of launches the per-launch figure averages over
+# (the engine, and the solver defaults such as the block length between convergence checks)
 TRAFFIC_SOURCES = ["paper_1804_07195_amd/csrc/hub_kernels.hip", "paper_1804_07195_amd/csrc/hub_internal.h",
-                   "paper_1804_07195_amd/csrc/hub_engine.hip", "paper_1804_07195_amd/csrc/hub_engine.h"]
+                   "paper_1804_07195_amd/csrc/hub_engine.hip", "paper_1804_07195_amd/csrc/hub_engine.h",
+                   "paper_1804_07195_amd/csrc/hub_api.hip"]
 
 
 def measured_traffic(kernel: str):

@@ -115,7 +115,7 @@ typedef struct {
 } hub_solve_opts;
 
 /* tol 1e-10, FP64 CG, max_iter 20000, m 10, a 5, inner_floor 1e-5, inner_max_iter 4000,
- * use_x0 0, check_every 16. */
+ * use_x0 0, check_every 8. */
 void hub_default_opts(hub_solve_opts *opts);
 
 typedef struct {

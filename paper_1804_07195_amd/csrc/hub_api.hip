@@ -264,7 +264,7 @@ void hub_default_opts(hub_solve_opts* o) {
   o->inner_a = 5.0;
   o->inner_floor = 1e-5;
   o->use_x0 = 0;
-  o->check_every = 16;
+  o->check_every = 8;
 }
 
 hub_status hub_create(hub_ctx** ctx, int device, size_t hbm_budget_bytes) {

@@ -67,7 +67,7 @@ def test_default_options(lib):
     from paper_1804_07195_amd import binding as b
     o = b.default_opts()
     assert (o.solver, o.max_iter, o.restart_m, o.inner_max_iter) == (b.HUB_CG_FP64, 20000, 10, 4000)
-    assert (o.tol, o.inner_a, o.inner_floor, o.use_x0, o.check_every) == (1e-10, 5.0, 1e-5, 0, 16)
+    assert (o.tol, o.inner_a, o.inner_floor, o.use_x0, o.check_every) == (1e-10, 5.0, 1e-5, 0, 8)
 
 
 def test_argument_errors_without_a_device(lib):
