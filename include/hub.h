@@ -327,10 +327,12 @@ hub_status hub_poll(hub_ctx *ctx, uint64_t ticket, int32_t *done, hub_solve_info
  * events on the solve's stream.  Stats are per kernel: "cg1_f64", "cg2_f64" (the
  * two kernels of an FP64 CG iteration) and "cg1_c64", "cg2_c64" (the same for the
  * complex64 inner CG).  bytes accumulates the algorithmic bytes of every timed
- * launch (per site: 80, 112, 40 and 56 bytes of distinct vector reads and writes,
- * the precomputed phase e^{i phi} included,
- * times the sites of the systems that iterated in that launch).  Timing adds an
- * event record around each launch; it is off by default.
+ * launch: per site the distinct vector reads and writes and the phase source
+ * (FP64: a 16-byte (cos, sin) pair, 80 bytes in stage 1, 80 or 128 in stage 2, the
+ * larger at the odd iterations that also update the solution; complex64: a 4-byte
+ * angle, 36 bytes in stage 1, 36 or 60 in stage 2), times the sites of the systems
+ * that iterated in that launch.  Timing adds an event record around each launch; it
+ * is off by default.
  * hub_profile_enable resets the stats; enable = 0 turns timing off. */
 typedef struct {
   char name[16];

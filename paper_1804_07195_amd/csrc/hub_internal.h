@@ -239,7 +239,7 @@ inline double cg_bytes(bool single, int stage, int it) {
   return kCgBytes[single ? 1 : 0][stage == 1 ? 0 : 1 + (it & 1)];
 }
 // Every reduction below leaves per-tile partials; a finalisation kernel (one
-// workgroup per system) sums them in a fixed order into sc->red[red_off..] and,
+// workgroup per system and value) sums them in a fixed order into sc->red[red_off..] and,
 // with RED_CG_SETUP, starts a CG on the result (pa, pr, pi of the launch list).
 // out = [b -] (M M^dagger + mu2) in, in one pass of the 12-point form (in: an FP64
 // slot or, with in_c64, a complex64 slot), |out|^2 (mode RED_NONE: no reduction).
