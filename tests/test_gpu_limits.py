@@ -8,7 +8,9 @@
   temporal hops of a site coincide) solve to the tolerance with both solvers and
   give the oracle's solution;
 * a batch of zero systems and a zero lattice extent are refused by the C ABI, and a
-  zero right-hand side gives x = 0 without iterating.
+  zero right-hand side gives x = 0 without iterating;
+* two host threads solving on one context, each on its own stream, get the results
+  of the same solves made alone, bit for bit.
 
 Bars as in the other parity tests: applies and force <= 1e-13 relative to
 max(1, max|y|); solves: the oracle's recomputed true residual <= 1e-10 and the
@@ -160,3 +162,40 @@ def test_empty_and_zero_inputs(hub):
                                      opts=hb.default_opts(solver=solver))
         assert st == hb.HUB_OK and torch.count_nonzero(xs) == 0
         assert all(i["converged"] == 1 and i["inner_iters"] == 0 for i in infos)
+
+
+def test_concurrent_host_threads_on_one_context(hub):
+    """Two host threads solving on one context, each on its own stream (the context
+    serialises its synchronous calls): every result is bit-identical to the same solve
+    made alone."""
+    import threading
+    hl, ol = lattices(12, 12, 16, 0.25)
+    jobs = []
+    for seed in range(4):
+        phi, eta = _inputs(ol, 2, 50 + seed, scale=0.9)
+        pd = dev(phi)
+        jobs.append((pd, hb.hub_apply_Mdag(hub, hl, pd, dev(eta)), "cg" if seed % 2 else "fgmres"))
+    alone = [host(hb.hub_solve(hub, hl, pd, [0.0, 0.1], chi, opts=hb.default_opts(solver=sv))[0])
+             for pd, chi, sv in jobs]
+    got, errors = {}, []
+
+    def work(k0):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for k in range(k0, len(jobs), 2):
+                    pd, chi, sv = jobs[k]
+                    x, _, _ = hb.hub_solve(hub, hl, pd, [0.0, 0.1], chi, opts=hb.default_opts(solver=sv), stream=s)
+                    s.synchronize()
+                    got[k] = x.cpu().numpy()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    ts = [threading.Thread(target=work, args=(k0,)) for k0 in (0, 1)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not errors and len(got) == len(jobs)
+    for k in range(len(jobs)):
+        assert np.array_equal(got[k], alone[k]), k
