@@ -150,11 +150,12 @@ def main(argv=None) -> None:
     import time
     ap = argparse.ArgumentParser(description="4-site benchmark of Sec. 7.2: HMC ensembles at several N_t, "
                                              "quasi-particle energies and their delta -> 0 limit")
-    ap.add_argument("--nt", type=int, nargs="+", default=[32, 64, 128])
-    ap.add_argument("--chains", type=int, default=32)
-    ap.add_argument("--therm", type=int, default=50)
-    ap.add_argument("--meas", type=int, default=200)
-    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--nt", type=int, nargs="+", default=[32, 64, 128],
+                    help="time slices of each ensemble (beta kappa = 8, so delta = 8 / N_t)")
+    ap.add_argument("--chains", type=int, default=32, help="Markov chains advanced in lockstep on the GPU")
+    ap.add_argument("--therm", type=int, default=50, help="thermalisation trajectories per chain")
+    ap.add_argument("--meas", type=int, default=200, help="measured trajectories per chain")
+    ap.add_argument("--seed", type=int, default=1, help="seed of the chains' random numbers")
     args = ap.parse_args(argv)
     results = []
     for nt in args.nt:
