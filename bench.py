@@ -51,20 +51,21 @@ APPLY_BYTES = 40.0       # x (16) + phi (8) in, y (16) out, FP64
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-hasenbusch", action="store_true")
-    ap.add_argument("--no-hmc", action="store_true")
-    ap.add_argument("--no-multishift", action="store_true")
-    ap.add_argument("--no-four-site", action="store_true")
+    ap.add_argument("--gpus", type=int, default=1, help="GPUs to use (this build runs on one)")
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (one step: the two 102x102x64 solves + S + dS/dphi)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed steps before the timed ones")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--no-hasenbusch", action="store_true", help="skip the Hasenbusch leg")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the HMC trajectory leg")
+    ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift leg")
+    ap.add_argument("--no-four-site", action="store_true", help="skip the 4-site ensemble leg")
     ap.add_argument("--counter-run", action="store_true",
                     help="target for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then one "
                          "step and nothing else")
-    ap.add_argument("--serving-requests", type=int, default=120)
-    ap.add_argument("--cpu-budget-s", type=float, default=25.0)
+    ap.add_argument("--serving-requests", type=int, default=120, help="requests in the serving stream")
+    ap.add_argument("--cpu-budget-s", type=float, default=25.0,
+                    help="CPU seconds the oracle baseline may spend on its slowest system")
     return ap.parse_args()
 
 
