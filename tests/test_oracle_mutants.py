@@ -150,6 +150,20 @@ CASES = [
     ("gauge action factor", "oracle.hmc:gauge_action",
      [("0.5 * float(np.sum(p * p)) / U_t", "float(np.sum(p * p)) / U_t", 0)], ["test_oracle_hmc"]),
     ("Metropolis direction", "oracle.hmc:hmc_update", [("u < np.exp(-dH)", "u < np.exp(dH)", 0)], ["test_oracle_hmc"]),
+    ("nested odd half step misplaced", "oracle.hmc:Integrator",
+     [("            for _ in range(j):\n                self._step(k + 1, self.H[k + 1])\n            if odd:\n"
+       "                self._half_step(k + 1, self.H[k + 1], first=True)",
+       "            if odd:\n                self._half_step(k + 1, self.H[k + 1], first=True)\n"
+       "            for _ in range(j):\n                self._step(k + 1, self.H[k + 1])", 0)], ["test_oracle_hmc"]),
+    ("nested odd ratio dropped", "oracle.hmc:Integrator", [("j, odd = divmod(r, 2)", "j, odd = r // 2, 0", 0)],
+     ["test_oracle_hmc"]),
+    ("kinetic energy factor", "oracle.hmc:kinetic", [("0.5 * float(np.sum(p * p))", "float(np.sum(p * p))", 0)],
+     ["test_oracle_hmc"]),
+    ("true residual not relative", "oracle.solve:true_rel_residual",
+     [("return _norm(bf - A(xf)) / _norm(bf)", "return _norm(bf - A(xf))", 0)], OP),
+    ("M^-1 solve with the adjoint", "oracle.hasenbusch:solve_M",
+     [("x = spla.spsolve(build_M(lat, phi).tocsc(), bf.ravel())",
+       "x = spla.spsolve(build_M(lat, phi).conj().T.tocsc(), bf.ravel())", 0)], ["test_oracle_hasenbusch"]),
     # Sec. 5.1, 6.1 shifts and spectra
     ("CG-M alpha ratio inverted", "oracle.multishift:cg_multishift",
      [("a_s = a * z_next / z_cur[s]", "a_s = a * z_cur[s] / z_next", 0)], ["test_oracle_multishift"]),
@@ -163,6 +177,8 @@ CASES = [
      [("np.sqrt(bt[j]) / a[j]", "bt[j] / a[j]", 0)], ["test_oracle_multishift"]),
     ("Hasenbusch masses exponent", "oracle.multishift:hasenbusch_masses",
      [("((i + 1) / (n + 1))", "((i + 1) / n)", 0)], ["test_oracle_multishift"]),
+    ("spectrum extremes swapped", "oracle.multishift:spectrum_extremes",
+     [("return float(ev[0]), float(ev[-1])", "return float(ev[-1]), float(ev[0])", 0)], ["test_oracle_multishift"]),
     # Sec. 7.2 exact diagonalisation and correlators
     ("ED hopping not symmetric", "oracle.ed:hopping", [("h[b, a] -= kappa", "h[b, a] += kappa", 0)],
      ["test_oracle_ed"]),
@@ -177,6 +193,12 @@ CASES = [
     ("ED thermal weight", "oracle.ed:thermal_correlator",
      [("wm = np.exp(-(beta - tau) * ev)", "wm = np.exp(-beta * ev)", 0)],
      ["test_oracle_ed", "test_oracle_correlators"]),
+    ("quasi-particle level without degeneracy sum", "oracle.ed:quasiparticle_energies",
+     [("levels[-1][1] += w[j]", "pass", 0)], ["test_oracle_ed"]),
+    ("quasi-particle energy not relative to the ground state", "oracle.ed:quasiparticle_energies",
+     [("float(E - ev[0])", "float(E)", 0)], ["test_oracle_ed"]),
+    ("fit window ignored", "oracle.correlators:fit_energy", [("& (C > 0)", "& (C > 0) | (tau >= 0)", 0)],
+     ["test_oracle_correlators"]),
     ("correlator wrap sign", "oracle.correlators:propagator_correlator",
      [("sgn = -1.0 if t0 + k >= lat.Nt else 1.0", "sgn = 1.0", 0)], ["test_oracle_correlators"]),
     ("correlator overall sign", "oracle.correlators:propagator_correlator",
