@@ -113,6 +113,38 @@ def test_free_field_plane_wave_full_size(hub):
 
 
 @pytest.mark.parametrize("solver", ["cg", "fgmres"])
+def test_free_field_solve_full_size_closed_form(hub, solver):
+    """phi = 0 at 102x102x64: a sum of five plane waves is solved exactly by
+    x = sum_k b_k / (|a_k|^2 + kappa~^2 |f_k|^2 + mu^2) (each plane wave spans an
+    eigenspace of M M^dagger), for two shifts in one batch; no oracle solve."""
+    w = WORKLOADS["large2"]
+    hl, ol = of_workload(w)
+    t, i, j = np.meshgrid(np.arange(w.Nt), np.arange(w.L1), np.arange(w.L2), indexing="ij")
+    rng = np.random.default_rng(77)
+    k = w.kappa_t
+    b = np.zeros(ol.shape, complex)
+    parts = []
+    for (n1, n2, n) in ((0, 0, 0), (17, 34, 5), (3, 90, 31), (51, 51, 12), (34, 68, 63)):
+        th1, th2, om = 2 * math.pi * n1 / w.L1, 2 * math.pi * n2 / w.L2, math.pi * (2 * n + 1) / w.Nt
+        ph = np.exp(1j * (th1 * i + th2 * j + om * t))
+        uA, uB = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        psi = np.zeros(ol.shape, complex)
+        psi[:, 0], psi[:, 1] = uA * ph, uB * ph
+        a = np.exp(-1j * om) - 1
+        f = 1 + np.exp(-1j * th1) + np.exp(-1j * th2)
+        parts.append((psi, abs(a) ** 2 + k * k * abs(f) ** 2))
+        b += psi
+    mu2 = [0.0, 0.1]
+    x, info, st = hb.hub_solve(hub, hl, dev(np.zeros(ol.shape)), mu2, dev(np.stack([b, b])),
+                               opts=hb.default_opts(solver=solver))
+    assert st == hb.HUB_OK
+    xs = host(x)
+    for q, m in enumerate(mu2):
+        want = sum(psi / (lam + m) for psi, lam in parts)
+        assert rel2(xs[q], want) <= 1e-9, (q, rel2(xs[q], want))
+
+
+@pytest.mark.parametrize("solver", ["cg", "fgmres"])
 def test_solve_tiny(hub, solver):
     w = WORKLOADS["tiny"]
     hl, ol = of_workload(w)
