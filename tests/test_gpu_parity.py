@@ -144,6 +144,36 @@ def test_free_field_solve_full_size_closed_form(hub, solver):
         assert rel2(xs[q], want) <= 1e-9, (q, rel2(xs[q], want))
 
 
+def test_gauge_covariance_full_size(hub):
+    """Time-dependent gauge transformation at 102x102x64 (pinned in the oracle):
+    phi'_{A,t} = phi_{A,t} + al_t - al_{t-1}, phi'_{B,t} = phi_{B,t} + al_{t+1} - al_t
+    gives M[phi'] = D M[phi] D^dagger with D = diag(e^{i al_t}), so chi' = D chi solves
+    to x' = D x, with the same action and the same force."""
+    w = WORKLOADS["large2"]
+    hl, ol = of_workload(w)
+    phi, eta = draw_inputs(w, batch=1)
+    rng = np.random.default_rng(91)
+    al = rng.normal(0.0, 1.5, size=w.Nt)
+    phi2 = phi.copy()
+    phi2[:, 0] += (al - np.roll(al, 1))[:, None, None]
+    phi2[:, 1] += (np.roll(al, -1) - al)[:, None, None]
+    d = np.exp(1j * al)[:, None, None, None]
+    pd, pd2 = dev(phi), dev(phi2)
+    chi = hb.hub_apply_Mdag(hub, hl, pd, dev(eta))
+    chi2 = dev(host(chi) * d[None])
+    opts = hb.default_opts(solver="fgmres")
+    x, _, st = hb.hub_solve(hub, hl, pd, [0.1], chi, opts=opts)
+    x2, _, st2 = hb.hub_solve(hub, hl, pd2, [0.1], chi2, opts=opts)
+    assert st == st2 == hb.HUB_OK
+    assert rel2(host(x2), host(x) * d[None]) <= 1e-8
+    S = hb.hub_action(hub, hl, chi, x)[0]
+    S2 = hb.hub_action(hub, hl, chi2, x2)[0]
+    assert abs(S2 - S) <= 1e-9 * abs(S)
+    F = host(hb.hub_force(hub, hl, pd, x))
+    F2 = host(hb.hub_force(hub, hl, pd2, x2))
+    assert rel2(F2, F) <= 1e-7
+
+
 @pytest.mark.parametrize("solver", ["cg", "fgmres"])
 def test_solve_tiny(hub, solver):
     w = WORKLOADS["tiny"]
