@@ -18,13 +18,20 @@
  *   or retains a caller buffer beyond its return, except hub_submit (see there).
  * Streams.  Calls taking a hipStream_t enqueue their kernels on that stream (0 =
  *   the null stream) and are stream-ordered with the caller's other work.
- *   hub_apply_* and hub_force return without synchronising.  hub_solve and
- *   hub_action synchronise the stream (they read small scalars back to the host).
+ *   hub_apply_*, hub_force and hub_force_sum return without synchronising.  The
+ *   solvers and hub_action synchronise the stream: the host drives the outer
+ *   iteration (Arnoldi steps, restarts, the true-residual tests) and reads a few
+ *   scalars back between kernels, so these calls return once their results are in.
  * Errors.  Every call returns a hub_status; HUB_OK is 0.  On failure
  *   hub_last_error() returns a message for the calling thread.  No call throws.
  *   Argument errors (null pointers, non-positive sizes, batch beyond
- *   HUB_MAX_BATCH, non-finite couplings or tolerances) return HUB_ERR_ARG before
- *   anything is enqueued.
+ *   HUB_MAX_BATCH, non-finite couplings or tolerances, an output buffer that
+ *   overlaps an input or another output) return HUB_ERR_ARG before anything is
+ *   enqueued.  The solvers also check the device data they are given: a
+ *   non-finite value in phi, the right-hand side or the initial guess shows in the
+ *   first reduction of the solve and ends that system with HUB_ERR_ARG
+ *   (converged = 0, the solution undefined).  The other calls do not inspect
+ *   device data: non-finite input gives non-finite output.
  */
 #ifndef HUB_H
 #define HUB_H
@@ -104,7 +111,7 @@ typedef enum {
 
 typedef struct {
   int32_t solver;          /* hub_solver                                                    */
-  int32_t max_iter;        /* CG: iteration limit; FGMRES: limit on restart cycles          */
+  int32_t max_iter;        /* CG: iteration limit; FGMRES: limit on restart cycles (exact)  */
   int32_t restart_m;       /* FGMRES restart length m (1..HUB_MAX_RESTART), paper: 10       */
   int32_t inner_max_iter;  /* iteration cap of each single-precision CG                     */
   double tol;              /* relative true-residual target ||b - A x|| / ||b||             */
@@ -146,6 +153,18 @@ hub_status hub_solve(hub_ctx *ctx, const hub_lattice *lat, const double *phi, co
 hub_status hub_force(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const hub_c128 *eta,
                      const hub_c128 *xi, double scale, int32_t accumulate, double *dSdphi,
                      int32_t batch, hipStream_t stream);
+
+/* dSdphi (+)= sum_b scale[b] * dS_b/dphi: the forces of a batch of pseudofermion terms
+ * on one phi (eqs. (p_dot), (eta_xi)), contracted as in hub_force and summed into one
+ * field, with phi, its phase and the temporal neighbour of each site evaluated once per
+ * site for the whole batch (molecular-dynamics kicks and the gradient of a sum of
+ * actions need only the sum).  eta: device [batch][N]; xi: device [batch][N] or NULL
+ * (then M^dagger eta is computed into library workspace); scale: host float64 [batch],
+ * finite; accumulate = 0 overwrites dSdphi, 1 adds to it.  dSdphi: device float64 [N],
+ * not overlapping phi, eta or xi. */
+hub_status hub_force_sum(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const hub_c128 *eta,
+                         const hub_c128 *xi, const double *scale, int32_t accumulate, double *dSdphi,
+                         int32_t batch, hipStream_t stream);
 
 /* S_b = Re chi_b^dagger eta_b, the pseudofermion action of eq. (hamiltonian) given
  * eta = (M M^dagger + mu2)^{-1} chi.  FP64 reduction with a fixed summation order.
@@ -316,11 +335,15 @@ typedef struct {
 } hub_request;
 
 /* Queue a request; returns at once with a ticket.  HUB_ERR_BUSY if the request alone
- * exceeds the serving budget, HUB_ERR_ARG for invalid fields. */
+ * exceeds the serving budget, HUB_ERR_ARG for invalid fields (x_out and dSdphi_out
+ * must not overlap each other, chi or phi). */
 hub_status hub_submit(hub_ctx *ctx, const hub_request *req, uint64_t *ticket);
-/* Never blocks.  *done = 1 once the request's outputs are written (then info, if not
- * NULL, is filled and the ticket is released); HUB_ERR_NOTFOUND for unknown tickets.
- * A finished request that missed its tolerance reports done with converged = 0. */
+/* Never blocks.  *done = 0 and HUB_OK while the request runs.  Once it is finished,
+ * *done = 1, info (if not NULL) is filled, the ticket is released and the return
+ * value is the request's own final status: HUB_OK; HUB_ERR_NOCONV if it missed its
+ * tolerance (x_out, S and the force then come from its last iterate); HUB_ERR_ARG if
+ * phi or chi held a non-finite value; HUB_ERR_HIP if a HIP call failed while it ran.
+ * Unknown tickets: HUB_ERR_NOTFOUND with *done = 0. */
 hub_status hub_poll(hub_ctx *ctx, uint64_t ticket, int32_t *done, hub_solve_info *info);
 
 /* Measurement: time every launch of the solver's CG-iteration kernels with HIP
@@ -345,6 +368,17 @@ hub_status hub_profile_enable(hub_ctx *ctx, int32_t enable);
 /* Copy up to `max` stats (synchronous solves on every stream of the context) into
  * out (host); *count receives the number written. */
 hub_status hub_profile_read(hub_ctx *ctx, hub_kernel_stat *out, int32_t max, int32_t *count);
+
+/* Measurement: a streaming kernel that moves exactly the bytes of one FP64 apply of n
+ * sites and does nothing else (per site: x and phi read, y = (Re x * phi, Im x + phi)
+ * written; no stencil, no phase; the apply's grid, tile and workgroup order).  It is
+ * the bandwidth ceiling hub_apply_M is compared with in the same process.  mode 0:
+ * plain loads and non-temporal stores (the store policy of hub_apply_M); 1:
+ * non-temporal loads and plain stores; 2: plain loads and stores.  phi: device
+ * float64 [n]; x, y: device [n], y not overlapping x or phi.  Returns without
+ * synchronising. */
+hub_status hub_profile_stream(hub_ctx *ctx, const double *phi, const hub_c128 *x, hub_c128 *y, int64_t n,
+                              int32_t mode, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -27,10 +27,10 @@ STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOC
                 5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
 
 SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_apply_Mdag", "hub_apply_normal",
-           "hub_default_opts", "hub_solve", "hub_force", "hub_action", "hub_submit", "hub_poll",
+           "hub_default_opts", "hub_solve", "hub_force", "hub_force_sum", "hub_action", "hub_submit", "hub_poll",
            "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
            "hub_md_schedule", "hub_hmc_trajectory", "hub_hmc_trajectories", "hub_solve_multishift",
-           "hub_hasenbusch_masses"]
+           "hub_hasenbusch_masses", "hub_profile_stream"]
 
 
 class HubLattice(ctypes.Structure):
@@ -122,6 +122,7 @@ def load() -> ctypes.CDLL:
     L.hub_solve.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
                             ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
     L.hub_force.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, i32, vp, i32, vp]
+    L.hub_force_sum.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, ctypes.POINTER(dbl), i32, vp, i32, vp]
     L.hub_action.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, i32, ctypes.POINTER(dbl), vp]
     L.hub_submit.argtypes = [vp, ctypes.POINTER(HubRequest), ctypes.POINTER(ctypes.c_uint64)]
     L.hub_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(HubSolveInfo)]
@@ -142,6 +143,7 @@ def load() -> ctypes.CDLL:
     L.hub_hasenbusch_masses.argtypes = [dbl, dbl, i32, ctypes.POINTER(dbl)]
     L.hub_profile_enable.argtypes = [vp, i32]
     L.hub_profile_read.argtypes = [vp, ctypes.POINTER(HubKernelStat), i32, ctypes.POINTER(i32)]
+    L.hub_profile_stream.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, vp]
     for name in SYMBOLS:
         fn = getattr(L, name)
         if name not in ("hub_last_error", "hub_default_opts"):
@@ -284,6 +286,27 @@ def hub_force(ctx: Context, lat: HubLattice, phi, eta, xi=None, scale: float = 1
     _check(load().hub_force(ctx.handle, ctypes.byref(lat), phi.data_ptr(), eta.data_ptr(),
                             None if xi is None else xi.data_ptr(), float(scale), 1 if accumulate else 0,
                             out.data_ptr(), nb, _stream(stream)))
+    return out
+
+
+def hub_force_sum(ctx: Context, lat: HubLattice, phi, eta, scale, xi=None, accumulate: bool = False, out=None,
+                  stream=None):
+    """sum_b scale[b] dS_b/dphi (float64 [N_t, 2, L1, L2]) for the batch eta_b = A_b^{-1} chi_b."""
+    _phi(phi, lat)
+    nb = _vec(eta, lat, "eta")
+    if xi is not None and _vec(xi, lat, "xi") != nb:
+        raise ValueError("xi must match eta")
+    sc = list(scale) if hasattr(scale, "__len__") else [scale] * nb
+    if len(sc) != nb:
+        raise ValueError("one scale per system")
+    sca = (ctypes.c_double * nb)(*[float(v) for v in sc])
+    if out is None:
+        out = torch.zeros(phi.shape, dtype=torch.float64, device=phi.device)
+    if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != phi.numel():
+        raise ValueError("out must be a contiguous float64 tensor shaped like phi")
+    _check(load().hub_force_sum(ctx.handle, ctypes.byref(lat), phi.data_ptr(), eta.data_ptr(),
+                                None if xi is None else xi.data_ptr(), sca, 1 if accumulate else 0,
+                                out.data_ptr(), nb, _stream(stream)))
     return out
 
 
@@ -479,12 +502,19 @@ def hub_submit(ctx: Context, lat: HubLattice, mu2: float, phi, chi, x_out=None, 
 
 
 def hub_poll(ctx: Context, pending) -> tuple:
-    """(done, info dict or None); never blocks."""
+    """(done, info dict or None); never blocks.  A finished request's info carries its
+    final status under "status" (HUB_OK, HUB_ERR_NOCONV, HUB_ERR_ARG or HUB_ERR_HIP);
+    a failure of the call itself (unknown ticket) raises."""
     ticket = pending.ticket if isinstance(pending, Pending) else int(pending)
-    done = ctypes.c_int32()
+    done = ctypes.c_int32(0)
     info = HubSolveInfo()
-    _check(load().hub_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(info)))
-    return bool(done.value), (info.as_dict() if done.value else None)
+    st = load().hub_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(info))
+    if not done.value:
+        _check(st)
+        return False, None
+    d = info.as_dict()
+    d["status"] = st
+    return True, d
 
 
 def hub_profile_enable(ctx: Context, enable: bool = True) -> None:
@@ -510,7 +540,7 @@ class PseudofermionAction(torch.autograd.Function):
     """phi -> S_b = Re chi_b^dagger (M M^dagger + mu2_b)^{-1} chi_b (eq. (hamiltonian)).
 
     forward: hub_solve + hub_action; backward: grad_phi = sum_b grad_S[b] dS_b/dphi
-    by hub_force (xi = M^dagger eta computed inside), accumulated over the batch."""
+    by one hub_force_sum over the batch (xi = M^dagger eta computed inside)."""
 
     @staticmethod
     def forward(ctx_, phi, chi, mu2, hub_ctx: Context, lat: HubLattice, opts=None):
@@ -525,10 +555,7 @@ class PseudofermionAction(torch.autograd.Function):
     def backward(ctx_, grad_S):
         phi, x = ctx_.saved_tensors
         hub_ctx, lat = ctx_.hub
-        g = grad_S.detach().to("cpu", torch.float64).tolist()
-        n = 2 * lat.L1 * lat.L2 * lat.Nt
-        xs = x.reshape(-1, n)
-        out = torch.zeros(phi.shape, dtype=torch.float64, device=phi.device)
-        for b, gb in enumerate(g):
-            hub_force(hub_ctx, lat, phi, xs[b].contiguous(), scale=gb, accumulate=True, out=out)
+        g = grad_S.detach().to("cpu", torch.float64).reshape(-1).tolist()
+        # one launch for the batch: sum_b grad_S[b] dS_b/dphi
+        out = hub_force_sum(hub_ctx, lat, phi, x, g)
         return out, None, None, None, None, None

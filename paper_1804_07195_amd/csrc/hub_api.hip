@@ -31,6 +31,12 @@ hub_status hip_fail(hipError_t e, const char* where) {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b || na == 0 || nb == 0) return false;
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
 hub_status check_lattice(const hub_lattice* lat) {
   if (!lat) return fail(HUB_ERR_ARG, "lattice is NULL");
   if (lat->L1 < 1 || lat->L2 < 1 || lat->Nt < 1)
@@ -71,6 +77,7 @@ struct Ticket {
   System sys;
   std::atomic<int> state{0};  // 0 queued, 1 running, 2 done
   hub_solve_info info{};
+  hub_status status = HUB_OK;  // final status, reported by hub_poll once done
 };
 
 
@@ -140,8 +147,12 @@ class Server {
     }
     *done = 1;
     if (info) *info = it->second->info;
+    const hub_status st = it->second->status;
     tickets_.erase(it);
-    return HUB_OK;
+    if (st == HUB_ERR_NOCONV) set_error("iteration limit reached before the tolerance");
+    if (st == HUB_ERR_ARG) set_error("non-finite value in phi, chi or the initial guess");
+    if (st == HUB_ERR_HIP) set_error("a HIP runtime call failed while the request ran");
+    return st;
   }
 
  private:
@@ -176,8 +187,16 @@ class Server {
         System& s = t->sys;
         Ticket* tp = t.get();
         s.on_done = [this, tp](System* sp) { complete(tp, sp); };
-        if (!engine_->add(&s)) {
-          back.push_back(id);  // retried once running requests release workspace
+        const Engine::AddResult ar = engine_->add(&s);
+        if (ar == Engine::ADD_NO_ROOM) {
+          back.push_back(id);  // retried once running requests release workspace or slots
+          continue;
+        }
+        if (ar != Engine::ADD_OK) {
+          // a HIP failure while joining: the request ends with that status
+          t->status = HUB_ERR_HIP;
+          t->info = hub_solve_info{};
+          t->state = 2;
           continue;
         }
         t->state = 1;
@@ -196,6 +215,7 @@ class Server {
         // a HIP failure: fail every running request
         for (auto& t : running_) {
           t->sys.status = HUB_ERR_HIP;
+          t->status = HUB_ERR_HIP;
           t->info = t->sys.info;
           t->info.converged = 0;
           engine_->remove(&t->sys);
@@ -212,8 +232,16 @@ class Server {
   void complete(Ticket* t, System* s) {
     double S = 0.0;
     const hub_request& r = t->req;
-    if (engine_->finalize(s, (const double2*)r.chi, r.dSdphi_out, &S) != hipSuccess) s->info.converged = 0;
+    hub_status st = s->status;
+    if (st == HUB_OK || st == HUB_ERR_NOCONV) {
+      // S and the force from the (last) iterate
+      if (engine_->finalize(s, (const double2*)r.chi, r.dSdphi_out, &S) != hipSuccess) {
+        s->info.converged = 0;
+        st = HUB_ERR_HIP;
+      }
+    }
     if (r.S_out) *r.S_out = S;
+    t->status = st;
     t->info = s->info;
     engine_->remove(s);
     t->state = 2;
@@ -308,10 +336,12 @@ static hub_status apply_common(hub_ctx* ctx, const hub_lattice* lat, const doubl
   if (s) return s;
   if ((s = check_batch(batch))) return s;
   if (!phi || !x || !y) return fail(HUB_ERR_ARG, "NULL buffer");
-  if ((const void*)x == (const void*)y) return fail(HUB_ERR_ARG, "x and y must not overlap");
-  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
-  HUB_HIP(launch_apply(g, phi, (const double2*)x, (double2*)y, batch, dag, st), "apply launch");
+  const size_t vb = (size_t)batch * g.n * sizeof(hub_c128);
+  if (overlaps(x, vb, y, vb) || overlaps(phi, (size_t)g.n * 8, y, vb))
+    return fail(HUB_ERR_ARG, "y must not overlap x or phi");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  HUB_HIP(launch_apply(g, phi, (const double2*)x, (double2*)y, batch, dag, st, true), "apply launch");
   return HUB_OK;
 }
 
@@ -333,7 +363,12 @@ hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* 
   if (s) return s;
   if ((s = check_batch(batch))) return s;
   if (!phi || !x || !y || !mu2) return fail(HUB_ERR_ARG, "NULL buffer");
-  if ((const void*)x == (const void*)y) return fail(HUB_ERR_ARG, "x and y must not overlap");
+  {
+    const Geom gg = make_geom(*lat);
+    const size_t vb = (size_t)batch * gg.n * sizeof(hub_c128);
+    if (overlaps(x, vb, y, vb) || overlaps(phi, (size_t)gg.n * 8, y, vb))
+      return fail(HUB_ERR_ARG, "y must not overlap x or phi");
+  }
   double m2[kMaxSys] = {0};
   for (int b = 0; b < batch; ++b) {
     if (!is_finite(mu2[b]) || mu2[b] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
@@ -388,8 +423,9 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
     sy.ph64 = phase[sy.phi].first;
     sy.ph32 = phase[sy.phi].second;
     sy.opts = o;
-    if (!eng->add(&sy)) {
-      result = fail(HUB_ERR_OOM, "solver workspace");
+    const Engine::AddResult ar = eng->add(&sy);
+    if (ar != Engine::ADD_OK) {
+      result = ar == Engine::ADD_HIP ? fail(HUB_ERR_HIP, get_error()) : fail(HUB_ERR_OOM, "solver workspace");
       break;
     }
     ++added;
@@ -411,8 +447,12 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
   hipError_t e = hipStreamSynchronize(stream);
   if (result != HUB_OK) return result;
   if (e != hipSuccess) return hip_fail(e, "solve");
+  // the first failure in this order of severity: non-finite input, then non-convergence
+  for (const System& sy : sys)
+    if (sy.status == HUB_ERR_ARG) result = HUB_ERR_ARG;
   for (const System& sy : sys)
     if (sy.status != HUB_OK && result == HUB_OK) result = sy.status;
+  if (result == HUB_ERR_ARG) set_error("non-finite value in phi, the right-hand side or the initial guess");
   if (result == HUB_ERR_NOCONV) set_error("iteration limit reached before the tolerance");
   return result;
 }
@@ -437,9 +477,14 @@ hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   if ((s = check_opts(o))) return s;
   for (int k = 0; k < batch; ++k)
     if (!is_finite(mu2[k]) || mu2[k] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+  const Geom g = make_geom(*lat);
+  {
+    const size_t vb = (size_t)batch * g.n * sizeof(hub_c128);
+    if (overlaps(b, vb, x, vb) || overlaps(phi, (size_t)g.n * 8, x, vb))
+      return fail(HUB_ERR_ARG, "x must not overlap b or phi");
+  }
   std::lock_guard<std::mutex> lk(ctx->mu);
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  const Geom g = make_geom(*lat);
   std::vector<System> sys((size_t)batch);
   for (int k = 0; k < batch; ++k) {
     sys[k].g = g;
@@ -449,7 +494,7 @@ hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
     sys[k].x = (double2*)(x + (size_t)k * g.n);
   }
   const hub_status result = run_solves(ctx, sys, o, stream);
-  if (result != HUB_OK && result != HUB_ERR_NOCONV) return result;
+  if (result != HUB_OK && result != HUB_ERR_NOCONV && result != HUB_ERR_ARG) return result;
   for (int k = 0; k < batch; ++k) info[k] = sys[k].info;
   return result;
 }
@@ -465,8 +510,13 @@ hub_status hub_force(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   if (!phi || !eta || !dSdphi) return fail(HUB_ERR_ARG, "NULL buffer");
   if (!is_finite(scale)) return fail(HUB_ERR_ARG, "scale must be finite");
   if (accumulate != 0 && accumulate != 1) return fail(HUB_ERR_ARG, "accumulate must be 0 or 1");
-  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
+  {
+    const size_t vb = (size_t)batch * g.n * sizeof(hub_c128), fb = (size_t)batch * g.n * 8;
+    if (overlaps(dSdphi, fb, eta, vb) || overlaps(dSdphi, fb, xi, vb) || overlaps(dSdphi, fb, phi, (size_t)g.n * 8))
+      return fail(HUB_ERR_ARG, "dSdphi must not overlap phi, eta or xi");
+  }
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   void* tmp = nullptr;
   if (!xi) {
     tmp = ctx->pool->alloc((size_t)batch * g.n * 16, stream);
@@ -480,6 +530,43 @@ hub_status hub_force(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   }
   hipError_t e = launch_force(g, phi, (const double2*)eta, (const double2*)xi, scale, accumulate, dSdphi, batch,
                               stream);
+  if (tmp) ctx->pool->release(tmp, stream);
+  if (e != hipSuccess) return hip_fail(e, "force launch");
+  return HUB_OK;
+}
+
+hub_status hub_force_sum(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* eta,
+                         const hub_c128* xi, const double* scale, int32_t accumulate, double* dSdphi, int32_t batch,
+                         hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !eta || !dSdphi || !scale) return fail(HUB_ERR_ARG, "NULL buffer");
+  for (int b = 0; b < batch; ++b)
+    if (!is_finite(scale[b])) return fail(HUB_ERR_ARG, "scale must be finite");
+  if (accumulate != 0 && accumulate != 1) return fail(HUB_ERR_ARG, "accumulate must be 0 or 1");
+  const Geom g = make_geom(*lat);
+  {
+    const size_t vb = (size_t)batch * g.n * sizeof(hub_c128), fb = (size_t)g.n * 8;
+    if (overlaps(dSdphi, fb, eta, vb) || overlaps(dSdphi, fb, xi, vb) || overlaps(dSdphi, fb, phi, fb))
+      return fail(HUB_ERR_ARG, "dSdphi must not overlap phi, eta or xi");
+  }
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  void* tmp = nullptr;
+  if (!xi) {
+    tmp = ctx->pool->alloc((size_t)batch * g.n * 16, stream);
+    if (!tmp) return HUB_ERR_OOM;
+    hipError_t e = launch_apply(g, phi, (const double2*)eta, (double2*)tmp, batch, true, stream);
+    if (e != hipSuccess) {
+      ctx->pool->release(tmp, stream);
+      return hip_fail(e, "xi launch");
+    }
+    xi = (const hub_c128*)tmp;
+  }
+  hipError_t e = launch_force_sum(g, phi, (const double2*)eta, (const double2*)xi, scale, accumulate, dSdphi, batch,
+                                  stream);
   if (tmp) ctx->pool->release(tmp, stream);
   if (e != hipSuccess) return hip_fail(e, "force launch");
   return HUB_OK;
@@ -521,6 +608,15 @@ hub_status hub_submit(hub_ctx* ctx, const hub_request* req, uint64_t* ticket) {
   if ((s = check_opts(req->opts))) return s;
   if (!req->phi || !req->chi || !req->x_out) return fail(HUB_ERR_ARG, "NULL buffer");
   if (!is_finite(req->mu2) || req->mu2 < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+  {
+    const size_t n = 2 * (size_t)req->lat.L1 * req->lat.L2 * req->lat.Nt;
+    const size_t vb = n * sizeof(hub_c128);
+    if (overlaps(req->chi, vb, req->x_out, vb) || overlaps(req->phi, n * 8, req->x_out, vb))
+      return fail(HUB_ERR_ARG, "x_out must not overlap chi or phi");
+    if (overlaps(req->dSdphi_out, n * 8, req->x_out, vb) || overlaps(req->dSdphi_out, n * 8, req->chi, vb) ||
+        overlaps(req->dSdphi_out, n * 8, req->phi, n * 8))
+      return fail(HUB_ERR_ARG, "dSdphi_out must not overlap x_out, chi or phi");
+  }
   Server* srv;
   {
     std::lock_guard<std::mutex> lk(ctx->server_mu);
@@ -552,6 +648,21 @@ hub_status hub_profile_enable(hub_ctx* ctx, int32_t enable) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->profiling = enable != 0;
   for (auto& kv : ctx->engines) kv.second->set_profiling(ctx->profiling);
+  return HUB_OK;
+}
+
+hub_status hub_profile_stream(hub_ctx* ctx, const double* phi, const hub_c128* x, hub_c128* y, int64_t n,
+                              int32_t mode, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  if (!phi || !x || !y) return fail(HUB_ERR_ARG, "NULL buffer");
+  if (n < 1 || n > (1LL << 30)) return fail(HUB_ERR_ARG, "n must be in [1, 2^30]");
+  if (mode < 0 || mode > 2) return fail(HUB_ERR_ARG, "mode must be 0, 1 or 2");
+  const size_t vb = (size_t)n * sizeof(hub_c128);
+  if (overlaps(x, vb, y, vb) || overlaps(phi, (size_t)n * 8, y, vb))
+    return fail(HUB_ERR_ARG, "y must not overlap x or phi");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  HUB_HIP(launch_stream_bytes(phi, (const double2*)x, (double2*)y, (int)n, mode, stream), "stream launch");
   return HUB_OK;
 }
 

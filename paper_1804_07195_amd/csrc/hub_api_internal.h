@@ -36,6 +36,9 @@ bool is_finite(double v);
 hub_status check_lattice(const hub_lattice* lat);
 hub_status check_batch(int32_t batch);
 hub_status check_opts(const hub_solve_opts& o);
+// True if the byte ranges [a, a + na) and [b, b + nb) intersect (device buffers of
+// one allocation space; empty ranges never intersect).
+bool overlaps(const void* a, size_t na, const void* b, size_t nb);
 // The engine that runs the synchronous solves enqueued on stream st.
 Engine* engine_for(hub_ctx* ctx, hipStream_t st);
 // Solves the prepared systems (each with its own geometry, phi, shift, right-hand

@@ -95,8 +95,10 @@ class Engine {
   ~Engine();
   // False if the engine's own device or pinned buffers could not be allocated.
   bool ok() const { return ok_; }
-  // Allocate workspace and join; false (with the error set) if over budget or full.
-  bool add(System* s);
+  // Allocate workspace and join.  ADD_NO_ROOM (with the error set): no free slot or
+  // the workspace is over budget; ADD_HIP: a HIP call failed while joining.
+  enum AddResult { ADD_OK = 0, ADD_NO_ROOM = 1, ADD_HIP = 2 };
+  AddResult add(System* s);
   // Remove a finished system and return its workspace to the pool.
   void remove(System* s);
   // Advance every system: host-side phases, then one block of CG iterations.
@@ -123,6 +125,8 @@ class Engine {
  private:
   // One host-side transition of a group of systems at the same phase.
   hipError_t group_phase(int phase, const std::vector<System*>& g);
+  // FP64 CG: the true residual of the iterates of g; restart or stop each system.
+  hipError_t confirm(const std::vector<System*>& g);
   // A block of CG iterations enqueued for the systems of one precision, whose
   // convergence flags are read back asynchronously.
   struct Block {

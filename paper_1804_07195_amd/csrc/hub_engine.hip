@@ -259,7 +259,7 @@ size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
          Pool::rounded(n * 4) + part;
 }
 
-bool Engine::add(System* s) {
+Engine::AddResult Engine::add(System* s) {
   int slot = -1;
   for (int k = 0; k < kMaxSys; ++k)
     if (!slots_[k]) {
@@ -268,7 +268,7 @@ bool Engine::add(System* s) {
     }
   if (slot < 0) {
     set_error("engine full");
-    return false;
+    return ADD_NO_ROOM;
   }
   const size_t n = (size_t)s->g.n;
   SysDesc& d = s->desc;
@@ -284,7 +284,7 @@ bool Engine::add(System* s) {
     if (p) s->owned.push_back(p);
     return p;
   };
-  bool ok = true;
+  bool ok = true, hip_ok = true;
   d.part = (double*)get((size_t)d.ntiles * (kMaxRed + 2) * sizeof(double));
   ok = ok && d.part;
   if (ok) {
@@ -325,7 +325,7 @@ bool Engine::add(System* s) {
     double2* p64 = (double2*)get(n * 16);
     float* p32 = want32 ? (float*)get(n * 4) : nullptr;
     ok = ok && p64 && (!want32 || p32);
-    if (ok && launch_phase(s->phi, p64, p32, (int)n, st_) != hipSuccess) ok = false;
+    if (ok && launch_phase(s->phi, p64, p32, (int)n, st_) != hipSuccess) ok = hip_ok = false;
     if (ok) {
       s->ph64 = p64;
       s->ph32 = p32;
@@ -336,7 +336,8 @@ bool Engine::add(System* s) {
   if (!ok) {
     for (void* p : s->owned) pool_->release(p, st_);
     s->owned.clear();
-    return false;
+    if (!hip_ok) set_error("phase launch failed");
+    return hip_ok ? ADD_NO_ROOM : ADD_HIP;
   }
   s->slot = slot;
   s->phase = PH_NEW;
@@ -348,9 +349,9 @@ bool Engine::add(System* s) {
     for (void* p : s->owned) pool_->release(p, st_);
     s->owned.clear();
     set_error("descriptor upload failed");
-    return false;
+    return ADD_HIP;
   }
-  return true;
+  return ADD_OK;
 }
 
 void Engine::remove(System* s) {
@@ -494,7 +495,10 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
         s->err = og.use_x0 ? std::sqrt(sc.red[2]) : std::sqrt(s->bb);
         if (og.use_x0) s->info.applies++;
         s->bnorm = std::sqrt(s->bb);
-        if (s->bnorm == 0.0) {
+        if (!std::isfinite(s->bb) || !std::isfinite(s->err)) {
+          // phi, b or the initial guess holds a non-finite value
+          finish(s, HUB_ERR_ARG);
+        } else if (s->bnorm == 0.0) {
           zero.push_back(s);
         } else if (s->err <= s->opts.tol * s->bnorm) {
           s->info.true_rel_resid = s->err / s->bnorm;
@@ -533,33 +537,18 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
       return hipSuccess;
     }
     case PH_CG_CONFIRM: {
-      // FP64 true residual of the CG iterate; restart the CG from x if it misses tol
-      LaunchList L = list(g);
-      for (size_t q = 0; q < g.size(); ++q) {
-        const System* s = g[q];
-        L.pa[q] = s->opts.tol * s->opts.tol * s->bb;
-        L.pr[q] = 0.0;
-        L.pi[q] = std::max(1, s->opts.max_iter - s->cg_total);
-      }
-      HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
-      HUB_TRY(read_scal(g));
+      // FP64 true residual of the CG iterate; restart the CG from x if it misses tol.
+      // |b|^2 comes from the CG start, whose reduction is NaN when phi or b holds a
+      // non-finite value: such systems stop here.
+      std::vector<System*> ok;
       for (System* s : g) {
-        const hub_solve_opts& o = s->opts;
-        s->info.applies++;
-        const double rr = h_scal_[s->slot].red[1];
-        s->info.true_rel_resid = s->bb > 0 ? std::sqrt(rr / s->bb) : 0.0;
-        if (s->info.true_rel_resid <= o.tol) {
-          finish(s, HUB_OK);
-        } else if (s->cg_total >= o.max_iter || !std::isfinite(rr)) {
-          finish(s, HUB_ERR_NOCONV);
-        } else {
-          s->info.outer_iters++;
-          s->enq = 0;
-          s->gen++;
-          s->phase = PH_CG_ITER;
-        }
+        if (!std::isfinite(s->bb))
+          finish(s, HUB_ERR_ARG);
+        else
+          ok.push_back(s);
       }
-      return hipSuccess;
+      if (ok.empty()) return hipSuccess;
+      return confirm(ok);
     }
     case PH_F_POST_INIT: {
       // x = z_0 (or x0 + z_0), r = b - A x, ERR = |r|
@@ -666,7 +655,7 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
         s->info.true_rel_resid = s->err / s->bnorm;
         if (s->err <= o.tol * s->bnorm) {
           finish(s, HUB_OK);
-        } else if (s->cycles >= std::min(o.max_iter, 1000) || !std::isfinite(s->err) || k == 0) {
+        } else if (s->cycles >= o.max_iter || !std::isfinite(s->err) || k == 0) {
           finish(s, HUB_ERR_NOCONV);
         } else {
           s->j = 0;
@@ -681,6 +670,40 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
     default:
       return hipSuccess;
   }
+}
+
+// FP64 true residual of the CG iterates of g (finite |b|^2); restart a CG from x where it
+// misses tol, or stop the system.
+hipError_t Engine::confirm(const std::vector<System*>& g) {
+  LaunchList L = list(g);
+  for (size_t q = 0; q < g.size(); ++q) {
+    const System* s = g[q];
+    L.pa[q] = s->opts.tol * s->opts.tol * s->bb;
+    L.pr[q] = 0.0;
+    L.pi[q] = std::max(1, s->opts.max_iter - s->cg_total);
+  }
+  HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_CG_SETUP, 1, st_));
+  HUB_TRY(read_scal(g));
+  for (System* s : g) {
+    const hub_solve_opts& o = s->opts;
+    s->info.applies++;
+    const double rr = h_scal_[s->slot].red[1];
+    s->info.true_rel_resid = s->bb > 0 ? std::sqrt(rr / s->bb) : 0.0;
+    if (s->info.true_rel_resid <= o.tol) {
+      finish(s, HUB_OK);
+    } else if (!std::isfinite(rr) && s->cg_total == 0) {
+      // r = b - A x0 is not finite before any iteration: phi or x0 is not finite
+      finish(s, HUB_ERR_ARG);
+    } else if (s->cg_total >= o.max_iter || !std::isfinite(rr)) {
+      finish(s, HUB_ERR_NOCONV);
+    } else {
+      s->info.outer_iters++;
+      s->enq = 0;
+      s->gen++;
+      s->phase = PH_CG_ITER;
+    }
+  }
+  return hipSuccess;
 }
 
 // Enqueue one block of CG iterations over every system that is iterating in the

@@ -357,7 +357,11 @@ hub_status hub_hasenbusch_heatbath(hub_ctx* ctx, const hub_lattice* lat, const d
   if (s) return s;
   if ((s = check_masses(mt, n))) return s;
   if (!phi || !rho || !chi || (n > 0 && !info)) return fail(HUB_ERR_ARG, "NULL buffer");
-  if ((const void*)rho == (const void*)chi) return fail(HUB_ERR_ARG, "rho and chi must not overlap");
+  {
+    const size_t nn = 2 * (size_t)lat->L1 * lat->L2 * lat->Nt, vb = (size_t)(n + 1) * nn * sizeof(hub_c128);
+    if (overlaps(rho, vb, chi, vb) || overlaps(phi, nn * 8, chi, vb))
+      return fail(HUB_ERR_ARG, "chi must not overlap rho or phi");
+  }
   hub_solve_opts o;
   hub_default_opts(&o);
   if (opts) o = *opts;
@@ -383,7 +387,12 @@ hub_status hub_hasenbusch_force(hub_ctx* ctx, const hub_lattice* lat, const doub
   if (s) return s;
   if ((s = check_masses(mt, n))) return s;
   if (!phi || !chi || !dSdphi || !eta || !info) return fail(HUB_ERR_ARG, "NULL buffer");
-  if ((const void*)chi == (const void*)eta) return fail(HUB_ERR_ARG, "chi and eta must not overlap");
+  {
+    const size_t nn = 2 * (size_t)lat->L1 * lat->L2 * lat->Nt, vb = (size_t)(n + 1) * nn * sizeof(hub_c128);
+    if (overlaps(chi, vb, eta, vb) || overlaps(phi, nn * 8, eta, vb) || overlaps(dSdphi, nn * 8, eta, vb) ||
+        overlaps(dSdphi, nn * 8, chi, vb) || overlaps(dSdphi, nn * 8, phi, nn * 8))
+      return fail(HUB_ERR_ARG, "eta and dSdphi must not overlap each other, chi or phi");
+  }
   if (term_mask == 0 || (n < 31 && (term_mask >> (n + 1)) != 0))
     return fail(HUB_ERR_ARG, "term_mask must select terms in [0, n]");
   if (!is_finite(scale)) return fail(HUB_ERR_ARG, "scale must be finite");
@@ -440,6 +449,12 @@ hub_status hub_hmc_trajectories(hub_ctx* ctx, const hub_lattice* lat, int32_t nc
   if (nchain < 1 || (long long)nchain * (params->n + 1) > HUB_MAX_BATCH)
     return fail(HUB_ERR_ARG, "nchain must be >= 1 with nchain * (n + 1) <= HUB_MAX_BATCH");
   if (!phi || !pi || !rho || !u || !info) return fail(HUB_ERR_ARG, "NULL buffer");
+  {
+    const size_t nn = 2 * (size_t)lat->L1 * lat->L2 * lat->Nt, fb = (size_t)nchain * nn * 8;
+    const size_t rb = (size_t)nchain * (params->n + 1) * nn * sizeof(hub_c128);
+    if (overlaps(phi, fb, pi, fb) || overlaps(phi, fb, rho, rb) || overlaps(pi, fb, rho, rb))
+      return fail(HUB_ERR_ARG, "phi, pi and rho must not overlap");
+  }
   for (int c = 0; c < nchain; ++c)
     if (!is_finite(u[c]) || u[c] < 0.0 || u[c] > 1.0) return fail(HUB_ERR_ARG, "u must be in [0, 1]");
   hub_solve_opts o;

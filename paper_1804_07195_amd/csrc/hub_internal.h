@@ -194,12 +194,20 @@ enum RedMode : int {
 // ---------------------------------------------------------------------------
 // Kernel launchers (hub_kernels.hip).  All enqueue on `st` and return the HIP error.
 // ---------------------------------------------------------------------------
+// y_b = M x_b or M^dagger x_b.  to_caller: y is the caller's result (stored
+// non-temporally); otherwise library workspace that a following kernel reads.
 hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch,
-                        bool dag, hipStream_t st);
+                        bool dag, hipStream_t st, bool to_caller = false);
 // out (+)= scale dS/dphi for eta and xi (minus `sub` when given: Hasenbusch ratio terms).
 hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, const double2* xi,
                         double scale, int accumulate, double* out, int batch, hipStream_t st,
                         const double2* sub = nullptr);
+// Measurement: a streaming kernel moving the bytes of one FP64 apply of n sites (mode 0:
+// non-temporal stores, 1: non-temporal loads, 2: plain).
+hipError_t launch_stream_bytes(const double* phi, const double2* x, double2* y, int n, int mode, hipStream_t st);
+// out (+)= sum_b scale_host[b] dS_b/dphi over a batch of eta, xi (out: one field of N).
+hipError_t launch_force_sum(const Geom& g, const double* phi, const double2* eta, const double2* xi,
+                            const double* scale_host, int accumulate, double* out, int batch, hipStream_t st);
 hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int batch, double* part,
                          double* result, hipStream_t st);
 // p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, phi reduced to [-pi, pi]

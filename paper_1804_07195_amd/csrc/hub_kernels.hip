@@ -569,8 +569,27 @@ __device__ __forceinline__ void store_active(Scal* sc, int v) {
 constexpr int kPubSites = 2;
 constexpr int kPubTile = kBlock * kPubSites;
 
+// Store of an operator result.  NT = true: a non-temporal store, for outputs handed
+// back to the caller (the result is not read again by this launch or the next one;
+// at 102x102x64 the public FP64 apply takes 8.1-8.6 us instead of 10.2 us with its
+// working set in the infinity cache and 13.7-14.2 us instead of 15.3 us with buffers
+// rotated past it).  NT = false: a plain store, for results a following kernel of the
+// library reads at once (xi for the force, the first pass of the normal operator),
+// which a non-temporal store would send past the infinity cache.
+template <bool NT>
+__device__ __forceinline__ void store_out(double2* p, double2 v) {
+  if constexpr (NT) {
+    hub_d2v w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (hub_d2v*)p);
+  } else {
+    *p = v;
+  }
+}
+
 // One vector per workgroup: all loads of a round in flight together, then the phase.
-template <bool DAG>
+template <bool DAG, bool NT>
 __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restrict__ phi,
                                                   const double2* __restrict__ x, double2* __restrict__ y,
                                                   int ntiles) {
@@ -581,13 +600,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   const int base = tile * kPubTile + threadIdx.x;
   auto ld = [=](int k) { return xb[k]; };
   auto pre = [](int) { return NoPre{}; };
-  auto post = [=](int n, double2 v, double2, NoPre) { yb[n] = v; };
+  auto post = [=](int n, double2 v, double2, NoPre) { store_out<NT>(yb + n, v); };
   stencil_sites<double, DAG, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{}, post);
 }
 
 // A group of `per` vectors per workgroup (separate kernel, so that the one-vector
 // kernel keeps its register budget).
-template <bool DAG>
+template <bool DAG, bool NT>
 __global__ __launch_bounds__(kBlock) void k_apply_grp(Geom g, const double* __restrict__ phi,
                                                       const double2* __restrict__ x, double2* __restrict__ y,
                                                       int ntiles, int per, int batch) {
@@ -625,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_grp(Geom g, const double* __re
 #pragma unroll
     for (int m = 0; m < kPubSites; ++m) {
       const double2 v = stencil_combine<double, DAG>(g, st[m], c[m], s[m], xs[m], xt[m], x0[m], x1[m], x2[m]);
-      if (ok[m]) yb[st[m].n] = v;
+      if (ok[m]) store_out<NT>(yb + st[m].n, v);
     }
   }
 }
@@ -817,6 +836,84 @@ __global__ __launch_bounds__(kBlock) void k_force_grp(Geom g, const double* __re
         *o = accumulate ? *o + scale * F : scale * F;
       }
     }
+  }
+}
+
+// Sum over the vectors of a batch: out (+)= sum_b scale_b F_b with F_b the force of
+// k_force.  phi, its phase and the temporal neighbour are evaluated once per site; per
+// site and vector only eta and xi (at the neighbour) are read, and out is written once.
+__global__ __launch_bounds__(kBlock) void k_force_sum(Geom g, const double* __restrict__ phi,
+                                                      const double2* __restrict__ eta,
+                                                      const double2* __restrict__ xi, Mu2Arr scale,
+                                                      int accumulate, double* __restrict__ out, int batch) {
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int base = tile * kTile + threadIdx.x;
+  const int P2 = 2 * g.P;
+#pragma unroll 2
+  for (int m = 0; m < kSitesPerThread; ++m) {
+    const int n = base + m * kBlock;
+    if (n >= g.n) break;
+    const uint32_t q2 = fdiv(fdiv((uint32_t)n, g.dL2), g.dL1);
+    const bool isA = (q2 & 1u) == 0;
+    const int t = (int)(q2 >> 1);
+    int tn;
+    double sgn;
+    if (isA) {
+      const bool wrap = t == 0;
+      tn = wrap ? n + (g.Nt - 1) * P2 : n - P2;
+      sgn = wrap ? -1.0 : 1.0;
+    } else {
+      const bool wrap = t == g.Nt - 1;
+      tn = wrap ? n - (g.Nt - 1) * P2 : n + P2;
+      sgn = wrap ? -1.0 : 1.0;
+    }
+    double c, s;
+    cis64(phi[n], c, s);
+    const double ec = sgn * c, es = sgn * (isA ? s : -s);
+    double F = 0.0;
+    for (int b = 0; b < batch; ++b) {
+      const size_t off = (size_t)b * g.n;
+      const double2 e = eta[off + n];
+      const double2 z = xi[off + tn];
+      // w = s e^{+-i phi} z ; F_b = 2 Im(conj(e) w)
+      const double wr = ec * z.x - es * z.y, wi = ec * z.y + es * z.x;
+      F = fma(scale.v[b], 2.0 * (e.x * wi - e.y * wr), F);
+    }
+    out[n] = accumulate ? out[n] + F : F;
+  }
+}
+
+// Measurement only: the bytes of one FP64 apply (x and phi read, y written per site)
+// with no stencil and no phase, two sites per thread, the apply's grid and workgroup
+// order.  NTL: non-temporal loads; NTS: non-temporal stores.
+template <bool NTL, bool NTS>
+__global__ __launch_bounds__(kBlock) void k_stream_bytes(const double* __restrict__ phi,
+                                                         const double2* __restrict__ x, double2* __restrict__ y,
+                                                         int n) {
+  const int l = xcd_remap(blockIdx.x, gridDim.x);
+  const int base = l * kPubTile + threadIdx.x;
+  double2 v[kPubSites];
+  double p[kPubSites];
+#pragma unroll
+  for (int m = 0; m < kPubSites; ++m) {
+    const int k = min(base + m * kBlock, n - 1);
+    if constexpr (NTL) {
+      const hub_d2v w = __builtin_nontemporal_load((const hub_d2v*)(x + k));
+      v[m].x = w.x;
+      v[m].y = w.y;
+      p[m] = __builtin_nontemporal_load(phi + k);
+    } else {
+      v[m] = x[k];
+      p[m] = phi[k];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kPubSites; ++m) {
+    const int k = base + m * kBlock;
+    double2 o;
+    o.x = v[m].x * p[m];
+    o.y = v[m].y + p[m];
+    if (k < n) store_out<NTS>(y + k, o);
   }
 }
 
@@ -1480,22 +1577,25 @@ __global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restric
 
 
 
-// x = 0, r = b; partial of |b|^2.
+// x = 0, r = b; partial of |b|^2, made NaN where the phase of phi is not finite (so
+// that a non-finite phi or b shows in the first reduction the host reads).
 template <int SPT>
 __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restrict__ sys, LaunchList L) {
   constexpr int TILE = kBlock * SPT;
   HUB_PROLOGUE_T(TILE)
   (void)sc;
-  const Vec<double2> b(d->vec[S_B]), x(d->vec[S_X]), r(d->vec[S_R]);
+  const Vec<double2> b(d->vec[S_B]), x(d->vec[S_X]), r(d->vec[S_R]), ph(d->ph64);
   double acc = 0.0;
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     if (n < g.n) {
       const double2 v = b[n];
+      const double2 e = ph[n];
       r.set(n, v);
       x.set(n, cz<double2>());
       acc += norm2<double>(v);
+      if (!isfinite(e.x) || !isfinite(e.y)) acc = __builtin_nan("");
     }
   }
   const double tot = block_sum(acc);
@@ -1700,22 +1800,31 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
 // ---------------------------------------------------------------------------
 static inline int tiles_of(int n) { return (n + kTile - 1) / kTile; }
 
-hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
-                        hipStream_t st) {
+template <bool NT>
+static void apply_nt(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
+                     hipStream_t st) {
   const int nt = (g.n + kPubTile - 1) / kPubTile;
   const int per = pub_group(nt, batch);
   const dim3 grid(nt * ((batch + per - 1) / per)), block(kBlock);
   if (per == 1) {
     if (dag)
-      hipLaunchKernelGGL(k_apply<true>, grid, block, 0, st, g, phi, x, y, nt);
+      hipLaunchKernelGGL((k_apply<true, NT>), grid, block, 0, st, g, phi, x, y, nt);
     else
-      hipLaunchKernelGGL(k_apply<false>, grid, block, 0, st, g, phi, x, y, nt);
+      hipLaunchKernelGGL((k_apply<false, NT>), grid, block, 0, st, g, phi, x, y, nt);
   } else {
     if (dag)
-      hipLaunchKernelGGL(k_apply_grp<true>, grid, block, 0, st, g, phi, x, y, nt, per, batch);
+      hipLaunchKernelGGL((k_apply_grp<true, NT>), grid, block, 0, st, g, phi, x, y, nt, per, batch);
     else
-      hipLaunchKernelGGL(k_apply_grp<false>, grid, block, 0, st, g, phi, x, y, nt, per, batch);
+      hipLaunchKernelGGL((k_apply_grp<false, NT>), grid, block, 0, st, g, phi, x, y, nt, per, batch);
   }
+}
+
+hipError_t launch_apply(const Geom& g, const double* phi, const double2* x, double2* y, int batch, bool dag,
+                        hipStream_t st, bool to_caller) {
+  if (to_caller)
+    apply_nt<true>(g, phi, x, y, batch, dag, st);
+  else
+    apply_nt<false>(g, phi, x, y, batch, dag, st);
   return hipGetLastError();
 }
 
@@ -1731,6 +1840,27 @@ hipError_t launch_force(const Geom& g, const double* phi, const double2* eta, co
   else
     hipLaunchKernelGGL(k_force_grp, grid, block, 0, st, g, phi, eta, xi, sub, scale, accumulate, out, nt, per,
                        batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_sum(const Geom& g, const double* phi, const double2* eta, const double2* xi,
+                            const double* scale_host, int accumulate, double* out, int batch, hipStream_t st) {
+  if (batch < 1 || batch > kMaxSys) return hipErrorInvalidValue;
+  Mu2Arr sc;
+  for (int b = 0; b < kMaxSys; ++b) sc.v[b] = b < batch ? scale_host[b] : 0.0;
+  hipLaunchKernelGGL(k_force_sum, dim3(tiles_of(g.n)), dim3(kBlock), 0, st, g, phi, eta, xi, sc, accumulate, out,
+                     batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_bytes(const double* phi, const double2* x, double2* y, int n, int mode, hipStream_t st) {
+  const dim3 grid((n + kPubTile - 1) / kPubTile), block(kBlock);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_stream_bytes<false, true>), grid, block, 0, st, phi, x, y, n);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_stream_bytes<true, false>), grid, block, 0, st, phi, x, y, n);
+  else
+    hipLaunchKernelGGL((k_stream_bytes<false, false>), grid, block, 0, st, phi, x, y, n);
   return hipGetLastError();
 }
 

@@ -63,6 +63,11 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   if (!phi || !mu2 || !b || !x || !info) return fail(HUB_ERR_ARG, "NULL buffer");
   for (int k = 0; k < nshift; ++k)
     if (!is_finite(mu2[k]) || mu2[k] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+  {
+    const size_t nn = 2 * (size_t)lat->L1 * lat->L2 * lat->Nt, vb = nn * sizeof(hub_c128);
+    if (overlaps(b, vb, x, (size_t)nshift * vb) || overlaps(phi, nn * 8, x, (size_t)nshift * vb))
+      return fail(HUB_ERR_ARG, "x must not overlap b or phi");
+  }
   hub_solve_opts o;
   hub_default_opts(&o);
   if (opts) o = *opts;

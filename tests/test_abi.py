@@ -29,7 +29,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_submit", "hub_poll",
+    for f in ["hub_apply_M", "hub_apply_Mdag", "hub_solve", "hub_force", "hub_force_sum", "hub_submit", "hub_poll",
               "hub_create", "hub_destroy", "hub_last_error", "hub_action", "hub_apply_normal", "hub_default_opts",
               "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
               "hub_md_schedule", "hub_hmc_trajectory", "hub_hmc_trajectories", "hub_solve_multishift", "hub_hasenbusch_masses"]:
