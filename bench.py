@@ -60,10 +60,13 @@ def parse():
     ap.add_argument("--no-hmc", action="store_true", help="skip the HMC trajectory leg")
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift leg")
     ap.add_argument("--no-four-site", action="store_true", help="skip the 4-site ensemble leg")
+    ap.add_argument("--no-batches", action="store_true",
+                    help="skip the 12x12x32 (16 right-hand sides) and 48x48x64 (3 shifts) solver comparison")
     ap.add_argument("--counter-run", action="store_true",
                     help="target for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then one "
                          "step and nothing else")
-    ap.add_argument("--serving-requests", type=int, default=120, help="requests in the serving stream")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="measured requests of the 200 req/s serving stream (after a warm-up of 200)")
     ap.add_argument("--cpu-budget-s", type=float, default=25.0,
                     help="CPU seconds the oracle baseline may spend on its slowest system")
     return ap.parse_args()
@@ -204,11 +207,12 @@ def main():
     opts = hb.default_opts(solver="fgmres", tol=w.tol)
     infos = []
 
-    def step():
-        _, info, _ = hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=opts)
+    ones = [1.0] * w.batch
+
+    def step(o=opts):
+        _, info, _ = hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=o)
         S = hb.hub_action(ctx, hl, chi, x)
-        for b in range(w.batch):
-            hb.hub_force(ctx, hl, pd, x[b].contiguous(), scale=1.0, accumulate=b > 0, out=dS)
+        hb.hub_force_sum(ctx, hl, pd, x, ones, out=dS)   # sum_b dS_b/dphi, one launch
         infos.append((info, S))
 
     for _ in range(args.warmup):
@@ -236,7 +240,7 @@ def main():
     value = w.batch * args.steps / elapsed
     last_info, last_S = infos[-1]
     resid = [i["true_rel_resid"] for i in last_info]
-    assert all(i["converged"] == 1 for i in last_info), last_info
+    assert all(i["converged"] == 1 and i["true_rel_resid"] <= w.tol for i in last_info), last_info
 
     # dominant kernel of the step (largest summed time among the timed CG kernels)
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
@@ -274,6 +278,20 @@ def main():
             raise RuntimeError("hub_apply_M failed: " + lib.hub_last_error().decode())
         return s.elapsed_time(e) / K, host_us
 
+    def timed_stream(args, K, mode):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        bad = 0
+        s.record()
+        for k in range(K):
+            p, x, y = args[k % len(args)]
+            bad |= lib.hub_profile_stream(ctx.handle, p, x, y, w.nsites, mode, sh)
+        e.record()
+        torch.cuda.synchronize()
+        if bad:
+            raise RuntimeError("hub_profile_stream failed: " + lib.hub_last_error().decode())
+        return s.elapsed_time(e) / K
+
     y = torch.empty_like(ed[0:1])
     hot_args = [(pd.data_ptr(), ed[0:1].data_ptr(), y.data_ptr())]
     timed_raw(hot_args, 5)
@@ -286,23 +304,45 @@ def main():
     timed_raw(cold_args, nrot)
     cold_ms, cold_host = timed_raw(cold_args, 20 * nrot)
     apply_bytes = w.nsites * APPLY_BYTES
+    gbps = lambda ms: round(apply_bytes / (ms * 1e-3) / 1e9, 1)
+    # the same bytes through a kernel with no stencil: the ceiling of this process, both
+    # cache policies (non-temporal stores as the apply; non-temporal loads)
+    ceiling = {}
+    for mode, tag in ((0, "nt_store"), (1, "nt_load")):
+        timed_stream(hot_args, 5, mode)
+        h = timed_stream(hot_args, 200, mode)
+        timed_stream(cold_args, nrot, mode)
+        c = timed_stream(cold_args, 20 * nrot, mode)
+        ceiling[tag] = {"hot_us": round(1e3 * h, 3), "hot_GBps": gbps(h), "cold_us": round(1e3 * c, 3),
+                        "cold_GBps": gbps(c)}
+    best_hot = min(v["hot_us"] for v in ceiling.values())
+    best_cold = min(v["cold_us"] for v in ceiling.values())
     m_apply = {"kernel": "k_apply<M>", "alg_bytes": int(apply_bytes),
-               "hot_us": round(1e3 * hot_ms, 3), "hot_GBps": round(apply_bytes / (hot_ms * 1e-3) / 1e9, 1),
-               "cold_us": round(1e3 * cold_ms, 3), "cold_GBps": round(apply_bytes / (cold_ms * 1e-3) / 1e9, 1),
-               "cold_buffers": nrot, "host_us_per_call": [round(hot_host, 2), round(cold_host, 2)]}
+               "hot_us": round(1e3 * hot_ms, 3), "hot_GBps": gbps(hot_ms),
+               "cold_us": round(1e3 * cold_ms, 3), "cold_GBps": gbps(cold_ms),
+               "cold_frac_of_peak": round(gbps(cold_ms) / HBM_PEAK_GBPS, 4),
+               "cold_buffers": nrot, "host_us_per_call": [round(hot_host, 2), round(cold_host, 2)],
+               "stream_ceiling": ceiling,
+               "frac_of_ceiling": {"hot": round(best_hot / (1e3 * hot_ms), 3),
+                                   "cold": round(best_cold / (1e3 * cold_ms), 3)}}
     del xs, ys, ps
 
-    # FP64 CG on the same systems, same accuracy
+    # FP64 CG on the same systems, the same step content (solve + S + summed force), the
+    # same final accuracy (every system's FP64 true residual <= tol)
     o64 = hb.default_opts(solver="cg", tol=w.tol)
-    hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=o64)
+    step(o64)
     torch.cuda.synchronize()
+    reps = 5
     t1 = time.perf_counter()
-    reps = 3
     for _ in range(reps):
-        _, info64, _ = hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=o64)
+        step(o64)
     torch.cuda.synchronize()
-    cg64 = {"solves_per_s": round(w.batch * reps / (time.perf_counter() - t1), 3),
-            "iters": [i["inner_iters"] for i in info64], "true_rel_resid": [i["true_rel_resid"] for i in info64]}
+    el64 = time.perf_counter() - t1
+    info64 = infos[-1][0]
+    assert all(i["converged"] == 1 and i["true_rel_resid"] <= w.tol for i in info64), info64
+    cg64 = {"solves_per_s": round(w.batch * reps / el64, 3), "ms_per_step": round(1e3 * el64 / reps, 3),
+            "iters": [i["inner_iters"] for i in info64], "true_rel_resid": [i["true_rel_resid"] for i in info64],
+            "step": "the same as the mixed step: solve + S + summed force"}
 
     out = {
         "metric": "M-apply HBM GB/s; solves/s at 1e-10 resid (102x102, Nt=64); p50/p99 latency",
@@ -322,6 +362,8 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in prof.items()},
     }
 
+    if not args.no_batches:
+        out["batches"] = batch_legs(ctx, hb, torch)
     if not args.no_hasenbusch:
         out["hasenbusch"] = hasenbusch_run(ctx, hb, torch)
     if not args.no_hmc:
@@ -336,6 +378,43 @@ def main():
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def batch_legs(ctx, hb, torch, reps: int = 7) -> dict:
+    """The two smaller batched workloads, each solved by FP64 CG and by the mixed
+    FGMRES to relative true residual 1e-10 on identical inputs: 12x12, N_t = 32 with 16
+    right-hand sides sharing phi (mu^2 = 0), and 48x48, N_t = 64 with the three
+    Hasenbusch shifts mu^2 in {0.5, 0.05, 0} in one launch.  Milliseconds per batch
+    (median over reps), iterations and the largest FP64 true residual of each."""
+    res = {}
+    for name in ("small16", "medium3"):
+        w = WORKLOADS[name]
+        hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
+        phi, eta = draw_inputs(w)
+        pd = torch.from_numpy(phi).to("cuda")
+        chi = hb.hub_apply_Mdag(ctx, hl, pd, torch.from_numpy(eta).to("cuda"))
+        x = torch.empty_like(chi)
+        mu2 = w.mu2_list()
+        row = {"workload": f"{w.L1}x{w.L2}x{w.Nt}, kappa={w.kappa}, U={w.U}, beta={w.beta}, {w.batch} systems, "
+                           f"mu2={mu2}", "sites_per_system": w.nsites}
+        for solver in ("cg", "fgmres"):
+            o = hb.default_opts(solver=solver, tol=w.tol)
+            hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=o)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                _, info, _ = hb.hub_solve(ctx, hl, pd, mu2, chi, x=x, opts=o)
+                ts.append(time.perf_counter() - t0)
+            assert all(i["converged"] == 1 and i["true_rel_resid"] <= w.tol for i in info), info
+            ms = 1e3 * sorted(ts)[len(ts) // 2]
+            row[solver] = {"ms_per_batch": round(ms, 3), "solves_per_s": round(w.batch / ms * 1e3, 1),
+                           "iters": [i["inner_iters"] for i in info],
+                           "cycles": [i["outer_iters"] for i in info],
+                           "max_true_rel_resid": max(i["true_rel_resid"] for i in info)}
+        row["mixed_speedup"] = round(row["cg"]["ms_per_batch"] / row["fgmres"]["ms_per_batch"], 3)
+        res[name] = row
+    return res
 
 
 def hasenbusch_run(ctx, hb, torch, reps: int = 5) -> dict:
@@ -485,43 +564,112 @@ def four_site_run() -> dict:
     return r
 
 
-def serving_run(ctx, hb, torch, nreq: int) -> dict:
-    """Replay a seeded Poisson stream (mean 200 req/s) of solve+S+force requests of mixed
-    lattice size, N_t and shift through hub_submit / hub_poll; report latency percentiles."""
-    stream = serving_stream(nreq, seed=5)
+def _serving_inputs(hb, torch, ctx, stream):
+    """Device inputs of each request of a serving stream, drawn on the device by torch's
+    seeded generator (the request's own seed): phi ~ N(0, U~) and chi = M^dagger eta with
+    eta complex Gaussian (Re, Im ~ N(0, 1/2)); output buffers allocated up front."""
     reqs = []
+    g = torch.Generator(device="cuda")
     for r in stream:
         w = r["workload"]
-        phi, eta = draw_inputs(w)
+        g.manual_seed(w.seed)
         hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
-        pd = torch.from_numpy(phi).to("cuda")
-        chi = hb.hub_apply_Mdag(ctx, hl, pd, torch.from_numpy(eta[0:1]).to("cuda"))
-        reqs.append((r["t"], w, hl, pd, chi))
+        pd = torch.randn(w.shape, dtype=torch.float64, device="cuda", generator=g) * math.sqrt(w.U_t)
+        er = torch.randn((1,) + w.shape, dtype=torch.float64, device="cuda", generator=g)
+        ei = torch.randn((1,) + w.shape, dtype=torch.float64, device="cuda", generator=g)
+        eta = torch.complex(er, ei) * math.sqrt(0.5)
+        chi = hb.hub_apply_Mdag(ctx, hl, pd, eta)
+        del er, ei, eta
+        reqs.append({"t": r["t"], "w": w, "hl": hl, "phi": pd, "chi": chi, "x": torch.empty_like(chi),
+                     "dS": torch.empty(w.shape, dtype=torch.float64, device="cuda")})
     torch.cuda.synchronize()
-    opts = hb.default_opts(solver="fgmres", tol=1e-10)
+    return reqs
+
+
+def _serve(hb, ctx, reqs, opts, times):
+    """Submit reqs[k] at times[k] (seconds from the start; all at once if None) and poll
+    until every request is done.  Returns per-request (latency s, status, converged),
+    the makespan and the mean number of requests in flight (submitted, not yet done)."""
     pend = {}
-    lat = []
+    out = [None] * len(reqs)
     t0 = time.perf_counter()
     k = 0
+    inflight_area = 0.0
+    last = t0
     while k < len(reqs) or pend:
-        now = time.perf_counter() - t0
-        while k < len(reqs) and reqs[k][0] <= now:
-            _, w, hl, pd, chi = reqs[k]
-            p = hb.hub_submit(ctx, hl, w.mu2[0], pd, chi, opts=opts)
-            pend[p.ticket] = (p, time.perf_counter())
+        now = time.perf_counter()
+        inflight_area += len(pend) * (now - last)
+        last = now
+        while k < len(reqs) and (times is None or times[k] <= now - t0):
+            r = reqs[k]
+            p = hb.hub_submit(ctx, r["hl"], r["w"].mu2[0], r["phi"], r["chi"], x_out=r["x"], dSdphi_out=r["dS"],
+                              opts=opts)
+            pend[k] = (p, time.perf_counter())
             k += 1
-        for tk in list(pend):
-            done, info = hb.hub_poll(ctx, pend[tk][0])
+        # poll at most 128 tickets per pass, oldest first (a long backlog would otherwise
+        # spend the pass in the poll calls)
+        for q in list(pend)[:128]:
+            done, info = hb.hub_poll(ctx, pend[q][0])
             if done:
-                lat.append((time.perf_counter() - pend[tk][1], info["converged"]))
-                del pend[tk]
-        time.sleep(0.0002)
-    total = time.perf_counter() - t0
-    ms = sorted(1e3 * l for l, _ in lat)
-    return {"requests": len(lat), "solves_per_s": round(len(lat) / total, 2),
-            "p50_ms": round(ms[len(ms) // 2], 2), "p99_ms": round(ms[min(len(ms) - 1, int(0.99 * len(ms)))], 2),
-            "converged": sum(c for _, c in lat), "offered_rate_per_s": 200,
-            "mix": "L in {6,12,24,48,102}, N_t in {16,32,64}, U~U[1,4], beta=N_t/4, mu2 in {0.5,0.1,0.01,0}"}
+                out[q] = (time.perf_counter() - pend[q][1], info["status"], info["converged"])
+                del pend[q]
+        time.sleep(0.0001)
+    span = time.perf_counter() - t0
+    return out, span, inflight_area / span
+
+
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(q * len(v)))]
+
+
+def serving_run(ctx, hb, torch, nreq: int, warm: int = 200) -> dict:
+    """Seeded Poisson stream (mean 200 req/s) of solve + S + force requests of mixed lattice
+    size, N_t and shift through hub_submit / hub_poll (continuous batching):
+    * latency percentiles over `nreq` requests after a warm-up window of `warm` requests;
+    * capacity: a backlog of the same requests submitted at once, drained as fast as the
+      engine admits them (sustained solves/s, requests in flight);
+    * offered-rate sweep: the stream replayed at 2x, 4x and 8x the rate."""
+    stream = serving_stream(warm + nreq, seed=5)
+    reqs = _serving_inputs(hb, torch, ctx, stream)
+    opts = hb.default_opts(solver="fgmres", tol=1e-10)
+    times = [r["t"] for r in reqs]
+    res, span, infl = _serve(hb, ctx, reqs, opts, times)
+    meas = res[warm:]
+    lat = [1e3 * l for l, _, _ in meas]
+    t_meas = times[-1] - times[warm]
+    ok = sum(1 for _, st, c in meas if st == 0 and c == 1)
+    out = {"requests": len(meas), "warmup_requests": warm, "offered_rate_per_s": 200,
+           "solves_per_s": round(len(meas) / max(t_meas, 1e-9), 2),
+           "p50_ms": round(_pct(lat, 0.50), 3), "p90_ms": round(_pct(lat, 0.90), 3),
+           "p99_ms": round(_pct(lat, 0.99), 3), "max_ms": round(max(lat), 3),
+           "converged": ok, "mean_in_flight": round(infl, 2),
+           "mix": "L in {6,12,24,48,102}, N_t in {16,32,64}, U~U[1,4], beta=N_t/4, mu2 in {0.5,0.1,0.01,0}; "
+                  "mixed FGMRES to 1e-10 + S + dS/dphi per request"}
+    # per lattice size: where the latency goes
+    by_L = {}
+    for r, (l, _, _) in zip(reqs[warm:], meas):
+        by_L.setdefault(r["w"].L1, []).append(1e3 * l)
+    out["p50_ms_by_L"] = {str(L): round(_pct(v, 0.5), 3) for L, v in sorted(by_L.items())}
+    # capacity: everything at once
+    cap, cspan, cinfl = _serve(hb, ctx, reqs[warm:], opts, None)
+    out["capacity"] = {"requests": len(cap), "solves_per_s": round(len(cap) / cspan, 2),
+                       "mean_in_flight": round(cinfl, 1),
+                       "converged": sum(1 for _, st, c in cap if st == 0 and c == 1)}
+    # offered-rate sweep over the first 600 measured requests, arrival times compressed
+    sweep = []
+    base = reqs[warm:warm + 600]
+    tb = [r["t"] - base[0]["t"] for r in base]
+    for f in (2, 4, 8):
+        rs, sp, fl = _serve(hb, ctx, base, opts, [t / f for t in tb])
+        l = [1e3 * v for v, _, _ in rs]
+        sweep.append({"offered_per_s": 200 * f, "achieved_per_s": round(len(rs) / sp, 1),
+                      "p50_ms": round(_pct(l, 0.5), 3), "p99_ms": round(_pct(l, 0.99), 3),
+                      "mean_in_flight": round(fl, 1)})
+    out["rate_sweep"] = sweep
+    del reqs
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -348,8 +348,10 @@ hub_status hub_poll(hub_ctx *ctx, uint64_t ticket, int32_t *done, hub_solve_info
 
 /* Measurement: time every launch of the solver's CG-iteration kernels with HIP
  * events on the solve's stream.  Stats are per kernel: "cg1_f64", "cg2_f64" (the
- * two kernels of an FP64 CG iteration) and "cg1_c64", "cg2_c64" (the same for the
- * complex64 inner CG).  bytes accumulates the algorithmic bytes of every timed
+ * two kernels of an FP64 CG iteration of a tiled system), "cg1_c64", "cg2_c64" (the
+ * same for the complex64 inner CG), and "cgwg_f64", "cgwg_c64" (the single-workgroup
+ * kernel that runs a whole block of CG iterations of each system of at most 20480
+ * sites in one launch; its bytes are not counted: it is latency-bound).  bytes accumulates the algorithmic bytes of every timed
  * launch: per site the distinct vector reads and writes and the phase source
  * (FP64: a 16-byte (cos, sin) pair, 80 bytes in stage 1, 80 or 128 in stage 2, the
  * larger at the odd iterations that also update the solution; complex64: a 4-byte

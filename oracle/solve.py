@@ -119,7 +119,14 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
       recursive residual tau = max(TOL * a * |b| / ERR, inner_floor) (ERR = |b| for
       the initial solve); the floor keeps the request reachable in single precision.
     * h and y are complex; h_ij = v_i^H w (classical Gram-Schmidt: all projections
-      first, then one subtraction); ERR <- ERR * |w| after each Arnoldi step.
+      first, then one subtraction).
+    * ERR, the residual estimate the step's inner tolerance and the cycle's break
+      test use, is after each Arnoldi step the least-squares residual
+      min_y |(|r|, 0, ...) - h y| of the steps so far: the residual of the best
+      iterate of the cycle.  The printed update ERR <- ERR * |w| is that quantity
+      when each step's inner solve meets its tolerance (|w| is then the reduction the
+      solve achieved); after an unpreconditioned step (z_j = v_j) the product no
+      longer tracks the residual and ends cycles early.
     * The small least-squares problem min |(|r|, 0, ...) - h y| is solved with
       numpy's lstsq; the update runs over the Arnoldi steps actually completed.
     * Outer test: recomputed FP64 true residual |b - A x| <= TOL |b|.
@@ -127,8 +134,9 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
     Returns (x, info) with info = dict(outer=number of restart cycles,
     arnoldi=Arnoldi steps, inner_solves, inner_iters, true_rel_resid).  A list passed
     as `record` receives, per restart cycle, the cycle's start x0, its vectors v_j
-    and z_j and the values TOL a |b| / ERR of the inner-solve test (for tests of the
-    cycle's minimal-residual property and of how close that test came to 1)."""
+    and z_j, the values TOL a |b| / ERR of the inner-solve test and ERR after each step
+    (for tests of the cycle's minimal-residual property, of the residual estimate and
+    of how close the inner-solve test came to 1)."""
     M = build_M(lat, phi)
     A = NormalOperator(lat, phi, mu2, M=M)
     M32 = M.astype(np.complex64)
@@ -150,7 +158,7 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
     w = r.copy()
     while ERR > TOL * bnorm and info["outer"] < max_outer:
         rnorm = ERR
-        V, Z, ratios = [], [], []
+        V, Z, ratios, errs = [], [], [], []
         H = np.zeros((m + 1, m), dtype=np.complex128)
         k = 0
         for j in range(m):
@@ -175,7 +183,11 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
             for i in range(j + 1):
                 w = w - H[i, j] * V[i]
             H[j + 1, j] = _norm(w)
-            ERR = ERR * H[j + 1, j].real
+            e1 = np.zeros(j + 2, dtype=np.complex128)
+            e1[0] = rnorm
+            yj = np.linalg.lstsq(H[: j + 2, : j + 1], e1, rcond=None)[0]
+            ERR = _norm(e1 - H[: j + 2, : j + 1] @ yj)
+            errs.append(ERR)
             k = j + 1
             info["arnoldi"] += 1
         if k == 0:
@@ -185,7 +197,7 @@ def fgmres_alg_a1(lat: Lattice, phi, mu2: float, b, TOL: float = 1e-10, m: int =
         y = np.linalg.lstsq(H[: k + 1, :k], rhs, rcond=None)[0]
         if record is not None:
             record.append(dict(x0=x.copy(), V=[v.copy() for v in V[:k]], Z=[z.copy() for z in Z[:k]],
-                               ratio=list(ratios[:k])))
+                               ratio=list(ratios[:k]), err=list(errs[:k])))
         for i in range(k):
             x = x + y[i] * Z[i]
         r = bf - A(x)

@@ -670,10 +670,10 @@ hub_status hub_profile_read(hub_ctx* ctx, hub_kernel_stat* out, int32_t max, int
   set_error("");
   if (!ctx || !out || !count) return fail(HUB_ERR_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
-  static const char* names[2][2] = {{"cg1_f64", "cg2_f64"}, {"cg1_c64", "cg2_c64"}};
+  static const char* names[2][3] = {{"cg1_f64", "cg2_f64", "cgwg_f64"}, {"cg1_c64", "cg2_c64", "cgwg_c64"}};
   int n = 0;
   for (int sp = 0; sp < 2; ++sp)
-    for (int st = 0; st < 2; ++st) {
+    for (int st = 0; st < 3; ++st) {
       if (n >= max) break;
       hub_kernel_stat k;
       std::memset(&k, 0, sizeof(k));

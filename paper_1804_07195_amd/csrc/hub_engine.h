@@ -51,6 +51,9 @@ class Pool {
 
 // Block length (CG iterations between flag reads) near a system's expected end.
 constexpr int kTailBlock = 4;
+// Block length when only single-workgroup systems iterate (their kernel leaves the
+// block at convergence).
+constexpr int kWgBlockIters = 48;
 
 // Host-side state of one linear system (M M^dagger + mu2) x = b.
 struct System {
@@ -77,6 +80,7 @@ struct System {
   int enq = 0;          // CG iterations enqueued since the last CG setup
   int gen = 0;          // number of CG setups so far (tags in-flight blocks)
   int pred = 0;         // iterations of the system's previous CG run (0: none yet)
+  bool wg = false;      // CG iterations in the single-workgroup kernel (small systems)
   double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
   std::vector<std::complex<double>> H;  // (m+1) x m, column-major
   std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload
@@ -116,8 +120,8 @@ class Engine {
     double bytes = 0.0;
   };
   void set_profiling(bool on);
-  // [single][stage-1]
-  KernelStat stat[2][2];
+  // [single][kernel]: stage 1, stage 2 of the tiled CG; the single-workgroup CG block
+  KernelStat stat[2][3];
   // Serving epilogue of a converged system: S = Re chi^dagger x (host), and
   // dS/dphi into dSdphi (device, may be null).  Synchronises the stream.
   hipError_t finalize(System* s, const double2* chi, double* dSdphi, double* S);
@@ -133,8 +137,10 @@ class Engine {
     bool single = false;
     int k = 0;
     int buf = 0;
-    std::vector<System*> v;             // grouped by tile class
-    std::vector<int> cls_end;           // end of each class in v
+    std::vector<System*> v;             // grouped by tile class, then the single-workgroup systems
+    std::vector<int> cls_end;           // end of each tile class in v
+    int nwg = 0;                        // single-workgroup systems at the end of v
+    std::vector<hipEvent_t> wgev;       // start/stop of their launch (profiling)
     std::vector<int> gen;               // System::gen of each system at enqueue
     std::vector<std::vector<int>> its;  // iteration index per launch and system (profiling)
     std::vector<hipEvent_t> kev;        // kernel start/stop events (profiling)
@@ -167,8 +173,10 @@ class Engine {
   int next_buf_[2] = {0, 0};
 };
 
+// y = argmin |beta e_1 - H y| for the (k+1) x k upper Hessenberg H (column-major, leading
+// dimension ldh), by Givens rotations; *resid (if not NULL) receives the minimal residual.
 std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& H, int ldh, int k,
-                                                 double beta);
+                                                 double beta, double* resid = nullptr);
 
 Geom make_geom(const hub_lattice& lat);
 int ntiles_of(int n);

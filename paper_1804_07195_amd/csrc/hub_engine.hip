@@ -141,7 +141,7 @@ void Pool::release(void* p, hipStream_t st) {
 // the same minimiser with better conditioning).
 // ---------------------------------------------------------------------------
 std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<double>>& Hin, int ldh, int k,
-                                                 double beta) {
+                                                 double beta, double* resid) {
   using cd = std::complex<double>;
   std::vector<cd> H(Hin);
   std::vector<cd> gvec(k + 1, cd(0.0));
@@ -169,6 +169,8 @@ std::vector<std::complex<double>> hessenberg_lsq(const std::vector<std::complex<
     gvec[i] = c * u + s * v;
     gvec[i + 1] = -std::conj(s) * u + c * v;
   }
+  // the rotated right-hand side's last entry is the minimal residual
+  if (resid) *resid = std::abs(gvec[k]);
   std::vector<cd> y(k, cd(0.0));
   for (int i = k - 1; i >= 0; --i) {
     cd acc = gvec[i];
@@ -340,6 +342,7 @@ Engine::AddResult Engine::add(System* s) {
     return hip_ok ? ADD_NO_ROOM : ADD_HIP;
   }
   s->slot = slot;
+  s->wg = is_fgmres(s->opts) && wg_of(s->g.n);
   s->phase = PH_NEW;
   s->done = false;
   s->info = hub_solve_info{};
@@ -629,7 +632,13 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
         const double hn = std::sqrt(std::max(sc.red[2 * (j + 1)], 0.0));
         s->H[(size_t)j * (m + 1) + j + 1] = hn;
         s->wnorm = hn;
-        s->err *= hn;
+        // ERR: the residual of the best iterate of the cycle so far, the least-squares
+        // residual of the Arnoldi relation (Algorithm A.1's ERR * |w| is this quantity
+        // while every step's inner solve meets its tolerance, and not after an
+        // unpreconditioned step, where it ends cycles that have not converged)
+        double res = s->err;
+        (void)hessenberg_lsq(s->H, m + 1, j + 1, s->rnorm_cycle, &res);
+        s->err = res;
         s->j = j + 1;
         s->phase = (s->j == m) ? PH_F_LSQ : PH_F_ARNOLDI;
       }
@@ -712,10 +721,12 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
   launched = false;
   std::vector<System*> v;
   int k = 1 << 30;
+  bool any_tiled = false;
   for (System* s : slots_) {
     if (!s || s->done) continue;
     if ((single && s->phase == PH_F_INNER) || (!single && s->phase == PH_CG_ITER)) {
       v.push_back(s);
+      any_tiled = any_tiled || !(single && s->wg);
       int ks = std::max(1, s->opts.check_every);
       // near the iteration count of the system's previous CG run, enqueue short
       // blocks: launches after convergence return at once but still cost a launch
@@ -724,26 +735,37 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     }
   }
   if (v.empty()) return hipSuccess;
-  // systems by the tile size of their CG stages: one launch per size class
+  // Only single-workgroup systems iterating: their kernel stops by itself within a
+  // block, so long blocks cost nothing after convergence and save the per-block
+  // flag read-backs.
+  if (!any_tiled) k = std::max(k, kWgBlockIters);
+  // small systems run the whole block in one single-workgroup launch
+  std::vector<System*> wgs;
+  for (System* s : v)
+    if (single && s->wg) wgs.push_back(s);
+  // the others by the tile size of their CG stages: one launch per size class
   std::vector<System*> ordered;
   std::vector<int> cls_spt, cls_end;
   for (int spt : {(int)kSitesPerThread, (int)kSmallSpt}) {
     for (System* s : v)
-      if (s->desc.spt == spt) ordered.push_back(s);
+      if (!(single && s->wg) && s->desc.spt == spt) ordered.push_back(s);
     if (!ordered.empty() && (cls_end.empty() || (int)ordered.size() > cls_end.back())) {
       cls_spt.push_back(spt);
       cls_end.push_back((int)ordered.size());
     }
     if (kSmallSpt == kSitesPerThread) break;
   }
+  const int ntile = (int)ordered.size();
   v = ordered;
   const int ncls = (int)cls_spt.size();
   Block b;
   b.single = single;
   b.k = k;
   b.v = v;
+  b.v.insert(b.v.end(), wgs.begin(), wgs.end());
+  b.nwg = (int)wgs.size();
   b.cls_end = cls_end;
-  for (System* s : v) b.gen.push_back(s->gen);
+  for (System* s : b.v) b.gen.push_back(s->gen);
   b.buf = next_buf_[single ? 1 : 0];
   next_buf_[single ? 1 : 0] ^= 1;
   std::vector<LaunchList> Ls;
@@ -755,20 +777,41 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     for (size_t q = 0; q < vc.size(); ++q) L.pi[q] = single ? S_Z0 + vc[q]->j : S_X;
     Ls.push_back(L);
   }
+  auto take_event = [&](std::vector<hipEvent_t>& dst) -> hipError_t {
+    if (events_.empty()) {
+      hipEvent_t ev;
+      HUB_TRY(hipEventCreate(&ev));
+      events_.push_back(ev);
+    }
+    dst.push_back(events_.back());
+    events_.pop_back();
+    return hipSuccess;
+  };
   if (profiling_) {
-    for (int e = 0; e < 4 * k * ncls; ++e) {
-      if (events_.empty()) {
-        hipEvent_t ev;
-        HUB_TRY(hipEventCreate(&ev));
-        events_.push_back(ev);
-      }
-      b.kev.push_back(events_.back());
-      events_.pop_back();
+    for (int e = 0; e < 4 * k * ncls; ++e) HUB_TRY(take_event(b.kev));
+    if (b.nwg > 0) {
+      HUB_TRY(take_event(b.wgev));
+      HUB_TRY(take_event(b.wgev));
     }
   }
-  for (int it = 0; it < k; ++it) {
-    std::vector<int> its(v.size());
-    for (size_t q = 0; q < v.size(); ++q) its[q] = v[q]->enq++;
+  if (b.nwg > 0) {
+    WgList W;
+    std::memset(&W, 0, sizeof(W));
+    W.scal = d_scal_;
+    W.nsys = b.nwg;
+    for (int q = 0; q < b.nwg; ++q) {
+      System* s = wgs[q];
+      W.nmax = std::max(W.nmax, s->g.n);
+      W.sys[q] = s->slot;
+      W.pi[q] = single ? S_Z0 + s->j : S_X;
+      W.it[q] = s->enq;
+      s->enq += k;
+    }
+    HUB_TRY(launch_cg_wg(d_desc_, W, k, st_, profiling_ ? b.wgev[0] : nullptr, profiling_ ? b.wgev[1] : nullptr));
+  }
+  for (int it = 0; it < k && ntile > 0; ++it) {
+    std::vector<int> its(ntile);
+    for (int q = 0; q < ntile; ++q) its[q] = v[q]->enq++;
     for (int c = 0; c < ncls; ++c) {
       const int q0 = c == 0 ? 0 : cls_end[c - 1];
       for (int q = q0; q < cls_end[c]; ++q) Ls[c].it[q - q0] = its[q];
@@ -785,7 +828,7 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
       }
   }
   int lo = kMaxSys, hi = -1;
-  for (System* s : v) {
+  for (System* s : b.v) {
     lo = std::min(lo, s->slot);
     hi = std::max(hi, s->slot);
   }
@@ -831,8 +874,17 @@ hipError_t Engine::finish_block(Block& b) {
       }
     }
   }
+  if (profiling_ && b.wgev.size() == 2) {
+    float ms = 0.0f;
+    HUB_TRY(hipEventElapsedTime(&ms, b.wgev[0], b.wgev[1]));
+    KernelStat& ks = stat[single ? 1 : 0][2];
+    ks.launches++;
+    ks.ms += ms;
+  }
   for (hipEvent_t e : b.kev) events_.push_back(e);
+  for (hipEvent_t e : b.wgev) events_.push_back(e);
   b.kev.clear();
+  b.wgev.clear();
   for (size_t q = 0; q < b.v.size(); ++q) {
     System* s = b.v[q];
     const bool want = single ? (s->phase == PH_F_INNER) : (s->phase == PH_CG_ITER);

@@ -153,6 +153,29 @@ struct CgList {
 };
 constexpr int kSmallCg = 4;
 
+// Mixed-solver systems of at most kWgMaxSites sites run their complex64 CG in the
+// single-workgroup kernel (one workgroup of kWgBlock threads per system, all of its
+// state in registers and LDS, a block of iterations per launch); their other solver
+// kernels use the small tile class.  The limit: p and u in complex64 (2 x 8 bytes per
+// site) plus the reduction scratch fit in the 160 KB of LDS of a gfx950 CU, and a
+// thread holds at most kWgPerThread sites.
+constexpr int kWgBlock = 1024;
+constexpr int kWgPerThread = 10;
+constexpr int kWgMaxSites = 10200;
+static_assert(kWgMaxSites <= kWgBlock * kWgPerThread, "sites per thread");
+static_assert(2 * kWgMaxSites * 8 + (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
+inline bool wg_of(int n) { return n <= kWgMaxSites; }
+// Systems of one single-workgroup CG launch: workgroup k runs system sys[k] from
+// iteration it[k], solution slot pi[k]; nmax = the largest system (LDS per workgroup).
+struct WgList {
+  Scal* scal;
+  int nsys;
+  int nmax;
+  int sys[kMaxSys];
+  int pi[kMaxSys];
+  int it[kMaxSys];
+};
+
 // Tile class of a system: sites per thread of all its solver kernels.  Large systems
 // take kSitesPerThread (2048-site tiles: fewer workgroups, fixed costs spread over more
 // sites); a system below kBigSites takes kSmallSpt (512-site tiles), so that its grids
@@ -233,6 +256,10 @@ hipError_t launch_cg_iter(const SysDesc* sys, const LaunchList& L, bool single, 
 // kernel's own start and end timestamps into them (hipExtLaunchKernel).
 hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single, int stage, hipStream_t st,
                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// K iterations of the complex64 CG of every system of L, one workgroup per system
+// (small systems, see kWgMaxSites); optional start/stop events.
+hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t st,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Multi-shift CG: start (r = b, x = 0, x_s = 0, p_s = b, partial |b|^2), setup (one
 // workgroup: scalars), and the two stages of iteration `it` (shifted updates of step
 // it-1 ride in stage 1, where beta_{it-1} is known).

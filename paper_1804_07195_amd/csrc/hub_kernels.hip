@@ -1220,6 +1220,164 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
 }
 
 // ---------------------------------------------------------------------------
+// Single-workgroup complex64 CG for small systems, resident on one compute unit.
+// One workgroup of kWgBlock threads owns a system of at most kWgMaxSites sites and
+// runs up to K iterations of the same recurrence as k_cg1<float> / k_cg2<float> in one
+// launch.  Each thread keeps r and the solution of its sites (threadIdx.x + m *
+// kWgBlock, m < kWgPerThread) in registers, and the two vectors the stencil reads at
+// neighbouring sites, p and u = M^dagger p, live in LDS (2 x 8 bytes x 10,200 sites
+// fit in the 160 KB of a gfx950 CU); only the phase angles at the temporal neighbours
+// are read from memory inside the loop.  Kernel boundaries become workgroup barriers
+// and the reductions workgroup sums (wave64 butterflies, then the 16 wave results in
+// a fixed order), so an iteration costs LDS traffic and two barriers instead of two
+// launch floors and the vectors' round trips through L2.  An FP64 system of this size
+// does not fit (p and u would take 2 x 16 bytes per site): FP64 CG keeps the tiled
+// kernels.  The solution advances every iteration (x += alpha p).  Entry: r, x and
+// p_old (slot S_P32 + (it & 1)) from memory; exit: the same slots written back,
+// rrv[it & 1] = |r_it|^2, rrv[(it - 1) & 1] = |r_{it-1}|^2, and on a stop iters = it,
+// active = 0.
+// ---------------------------------------------------------------------------
+// Sum over the workgroup in a fixed order; every thread gets the value.
+__device__ __forceinline__ double wg_sum(double v) {
+  __shared__ double lds[kWgBlock / 64];
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kWgBlock / 64; ++k) s += lds[k];
+  return s;
+}
+
+__global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict__ sys, WgList L, int K) {
+  extern __shared__ float2 wlds[];  // p [nmax], u [nmax]
+  const int kk = blockIdx.x;
+  const SysDesc* __restrict__ d = sys + L.sys[kk];
+  Scal* sc = L.scal + L.sys[kk];
+  if (!load_active(sc)) return;
+  const Geom g = d->g;
+  const int N = g.n;
+  float2* __restrict__ lp = wlds;
+  float2* __restrict__ lu = wlds + L.nmax;
+  const int it0 = L.it[kk];
+  const float mu2 = (float)d->mu2;
+  const double stop2 = sc->stop2;
+  const int maxit = sc->maxit;
+  const Vec<float2> r(d->vec[S_R32]), x(d->vec[L.pi[kk]]);
+  const Angle32 phi(d->ph32);
+  float2 rv[kWgPerThread], xv[kWgPerThread];
+  float ang[kWgPerThread];
+  {
+    const Vec<float2> po(d->vec[S_P32 + (it0 & 1)]);
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      const int n = threadIdx.x + m * kWgBlock;
+      if (n < N) {
+        rv[m] = r[n];
+        xv[m] = x[n];
+        ang[m] = phi.load(n);
+        if (it0 > 0) lp[n] = po[n];
+      }
+    }
+  }
+  double rr = sc->rrv[it0 & 1];
+  double rr_prev = it0 > 0 ? sc->rrv[(it0 - 1) & 1] : 1.0;
+  int it = it0;
+  bool stopped = false;
+  __syncthreads();
+  for (int step = 0; step < K; ++step, ++it) {
+    // the stopping test of iteration it (at it = 0 the CG setup decided)
+    if (it > 0 && (!(rr > stop2) || it >= maxit)) {
+      stopped = true;
+      break;
+    }
+    const float beta = it == 0 ? 0.0f : (float)(rr / rr_prev);
+    float acc = 0.0f;
+    // p = r + beta p_old on this thread's sites
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      const int n = threadIdx.x + m * kWgBlock;
+      if (n < N) {
+        float2 pv = rv[m];
+        if (it > 0) {
+          const float2 q = lp[n];
+          pv.x = fmaf(beta, q.x, pv.x);
+          pv.y = fmaf(beta, q.y, pv.y);
+        }
+        lp[n] = pv;
+        acc += mu2 * norm2<float>(pv);
+      }
+    }
+    __syncthreads();
+    // u = M^dagger p (the phase at the temporal neighbour); <p, A p> = |u|^2 + mu2 |p|^2.
+    // The site index is laundered through an empty asm statement so that the neighbour
+    // indices of all sites are recomputed per pass rather than hoisted out of the
+    // iteration loop, where they would not fit in the registers.
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      int n = threadIdx.x + m * kWgBlock;
+      asm volatile("" : "+v"(n));
+      if (n < N) {
+        const SiteIdx st = site_index<true>(g, n);
+        const float a = phi.load(st.pn);
+        const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
+        float c, s;
+        cis32(a, c, s);
+        const float2 y = stencil_combine<float, true>(g, st, c, s, xs, xt, x0, x1, x2);
+        lu[n] = y;
+        acc += norm2<float>(y);
+      }
+    }
+    const double pap = wg_sum((double)acc);  // its barriers also publish u
+    const float alpha = (float)(rr / pap);
+    // q = M u + mu2 p; r -= alpha q; x += alpha p; |r|^2
+    float acc2 = 0.0f;
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      int n = threadIdx.x + m * kWgBlock;
+      asm volatile("" : "+v"(n));
+      if (n < N) {
+        const SiteIdx st = site_index<false>(g, n);
+        const float2 xs = lu[st.n], xt = lu[st.tn], x0 = lu[st.h0], x1 = lu[st.h1], x2 = lu[st.h2];
+        float c, s;
+        cis32(ang[m], c, s);
+        const float2 q = stencil_combine<float, false>(g, st, c, s, xs, xt, x0, x1, x2);
+        const float2 pv = lp[n];
+        rv[m].x -= alpha * fmaf(mu2, pv.x, q.x);
+        rv[m].y -= alpha * fmaf(mu2, pv.y, q.y);
+        xv[m].x = fmaf(alpha, pv.x, xv[m].x);
+        xv[m].y = fmaf(alpha, pv.y, xv[m].y);
+        acc2 += norm2<float>(rv[m]);
+      }
+    }
+    rr_prev = rr;
+    rr = wg_sum((double)acc2);
+  }
+  // write the state back: r, x, and p_{it-1} to the slot iteration `it` reads it from
+  {
+    const Vec<float2> pw(d->vec[S_P32 + (it & 1)]);
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      const int n = threadIdx.x + m * kWgBlock;
+      if (n < N) {
+        r.set(n, rv[m]);
+        x.set(n, xv[m]);
+        if (it > 0) pw.set(n, lp[n]);
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    sc->rrv[it & 1] = rr;
+    if (it > 0) sc->rrv[(it - 1) & 1] = rr_prev;
+    if (stopped) {
+      sc->iters = it;
+      store_active(sc, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Multi-shift CG (FP64).  Base CG on A_0 as k_cg1 / k_cg2; every shifted system s
 // follows with x_s += alpha^s_k p^s_k, p^s_{k+1} = zeta^s_{k+1} r_{k+1} + beta^s_k p^s_k,
 //   zeta^s_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
@@ -1985,6 +2143,24 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
   return hipGetLastError();
 }
 
+
+hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if (L.nsys < 1 || L.nsys > kMaxSys || K < 1 || L.nmax < 1 || L.nmax > kWgMaxSites) return hipErrorInvalidValue;
+  const size_t lds = 2 * (size_t)L.nmax * sizeof(float2);
+  static bool attr_set = false;  // the 160 KB of dynamic LDS exceed the default limit
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_cg_wg32, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(2 * (size_t)kWgMaxSites * sizeof(float2)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const dim3 grid(L.nsys), block(kWgBlock);
+  if (e0)
+    hipExtLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, e0, e1, 0, sys, L, K);
+  else
+    hipLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, sys, L, K);
+  return hipGetLastError();
+}
 
 hipError_t launch_publish(const Scal* d, Scal* h, int cnt, unsigned* flag, unsigned seq, hipStream_t st) {
   if (cnt < 1 || cnt > kMaxSys || !d || !h || !flag) return hipErrorInvalidValue;

@@ -122,6 +122,10 @@ CASES = [
      [("rhs[0] = rnorm", "rhs[0] = 1.0", 0)], OP),
     ("A.1 subdiagonal dropped", "oracle.solve:fgmres_alg_a1",
      [("H[j + 1, j] = _norm(w)", "H[j + 1, j] = 0.0 * _norm(w)", 0)], OP),
+    ("A.1 residual estimate as the product of subdiagonals", "oracle.solve:fgmres_alg_a1",
+     [("ERR = _norm(e1 - H[: j + 2, : j + 1] @ yj)", "ERR = ERR * H[j + 1, j].real", 0)], OP),
+    ("A.1 residual estimate not updated", "oracle.solve:fgmres_alg_a1",
+     [("ERR = _norm(e1 - H[: j + 2, : j + 1] @ yj)", "ERR = ERR", 0)], OP),
     ("A.1 one projection per step", "oracle.solve:fgmres_alg_a1",
      [("for i in range(j + 1):\n                w = w - H[i, j] * V[i]",
        "for i in range(j, j + 1):\n                w = w - H[i, j] * V[i]", 0)], OP),

@@ -393,6 +393,44 @@ def test_alg_a1_cycle_minimises_the_residual_over_the_z_vectors(mu2):
         assert np.linalg.norm(x1 - best) <= 1e-6 * np.linalg.norm(best)
 
 
+@pytest.mark.parametrize("mu2", [0.0, 0.05])
+def test_alg_a1_residual_estimate_is_the_cycle_residual(mu2):
+    """The residual estimate ERR after Arnoldi step j of a cycle is the true residual of
+    the best iterate of the cycle so far, |b - A (x0 + Z_j y)| minimised over y with
+    Z_j = [z_0 .. z_j], recomputed here from the dense operator (not from h).  A
+    product of subdiagonal entries in its place, or a missed update, fails it."""
+    w = WORKLOADS["tiny"]
+    lat = lat_of(w)
+    phi, eta = draw_inputs(w, batch=1)
+    chi = oracle.apply_Mdag(lat, phi, eta[0]).ravel()
+    Ad = NormalOperator(lat, phi, mu2).dense()
+    cycles = []
+    oracle.fgmres_alg_a1(lat, phi, mu2, chi, TOL=1e-10, inner_floor=1e-2, m=4, record=cycles)
+    steps = 0
+    for c in cycles:
+        r0 = chi - Ad @ c["x0"]
+        for j, err in enumerate(c["err"]):
+            Z = np.stack(c["Z"][: j + 1], axis=1)
+            best = c["x0"] + Z @ np.linalg.lstsq(Ad @ Z, r0, rcond=None)[0]
+            want = np.linalg.norm(chi - Ad @ best)
+            assert abs(err - want) <= 1e-6 * want + 1e-14 * np.linalg.norm(chi), (j, err, want)
+            steps += 1
+    assert steps >= 4
+
+
+def test_alg_a1_has_no_crawl_on_the_12x12x32_batch():
+    """On the 12x12, N_t = 32 workload (mu^2 = 0) the first cycle ends close to TOL;
+    with ERR the cycle's least-squares residual the solve then needs at most two
+    restart cycles (the printed product estimate took 21-26 one-step cycles there)."""
+    w = WORKLOADS["small16"]
+    lat = lat_of(w)
+    phi, eta = draw_inputs(w, batch=2)
+    for k in range(2):
+        chi = oracle.apply_Mdag(lat, phi, eta[k])
+        x, info = oracle.fgmres_alg_a1(lat, phi, 0.0, chi, TOL=1e-10)
+        assert info["true_rel_resid"] <= 1e-10 and info["outer"] <= 2, info
+
+
 def _read_golden(name):
     vals = {}
     with open(os.path.join(GOLDEN, name)) as f:
