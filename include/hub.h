@@ -104,6 +104,21 @@ hub_status hub_apply_Mdag(hub_ctx *ctx, const hub_lattice *lat, const double *ph
 hub_status hub_apply_normal(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mu2,
                             const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
 
+/* Bytes of the scratch array behind hub_apply_normal_noalloc (64 MiB per device). */
+#define HUB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* hub_apply_normal for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc): the same kernels and
+ * results, with the intermediate M^dagger x in a scratch array that the library holds
+ * on each device from the first hub_create on that device until the process ends,
+ * instead of context workspace.  Allocates nothing.  batch * N * 16 bytes must not
+ * exceed HUB_NOALLOC_SCRATCH_BYTES (else HUB_ERR_ARG; at 102x102x64 that is a batch
+ * of up to 3).  Every call on one device uses the same array: calls that overlap in
+ * time on one device (other streams, threads or contexts) race, and the caller must
+ * order them (one stream, or events).  Returns without synchronising. */
+hub_status hub_apply_normal_noalloc(hub_ctx *ctx, const hub_lattice *lat, const double *phi, const double *mu2,
+                                    const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
+
 typedef enum {
   HUB_CG_FP64 = 0,        /* double-precision CG (Sec. 3)                                 */
   HUB_FGMRES_MIXED = 1    /* FP64 flexible GMRES(m) with complex64 CG preconditioner (App. A) */

@@ -23,6 +23,7 @@ HUB_MAX_BATCH = 64
 HUB_MAX_RESTART = 20
 HUB_MAX_HB_MASSES = 16
 HUB_MAX_SHIFTS = 17
+HUB_NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {0: "HUB_OK", 1: "HUB_ERR_ARG", 2: "HUB_ERR_OOM", 3: "HUB_ERR_NOCONV", 4: "HUB_ERR_HIP",
                 5: "HUB_ERR_BUSY", 6: "HUB_ERR_NOTFOUND"}
 
@@ -30,7 +31,7 @@ SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_ap
            "hub_default_opts", "hub_solve", "hub_force", "hub_force_sum", "hub_action", "hub_submit", "hub_poll",
            "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
            "hub_md_schedule", "hub_hmc_trajectory", "hub_hmc_trajectories", "hub_solve_multishift",
-           "hub_hasenbusch_masses", "hub_profile_stream"]
+           "hub_hasenbusch_masses", "hub_profile_stream", "hub_apply_normal_noalloc"]
 
 
 class HubLattice(ctypes.Structure):
@@ -117,6 +118,7 @@ def load() -> ctypes.CDLL:
     for f in (L.hub_apply_M, L.hub_apply_Mdag):
         f.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, i32, vp]
     L.hub_apply_normal.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), vp, vp, i32, vp]
+    L.hub_apply_normal_noalloc.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), vp, vp, i32, vp]
     L.hub_default_opts.argtypes = [ctypes.POINTER(HubSolveOpts)]
     L.hub_default_opts.restype = None
     L.hub_solve.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
@@ -249,6 +251,19 @@ def hub_apply_normal(ctx: Context, lat: HubLattice, phi, mu2, x, y=None, stream=
     y = torch.empty_like(x) if y is None else y
     _check(load().hub_apply_normal(ctx.handle, ctypes.byref(lat), phi.data_ptr(), mu, x.data_ptr(), y.data_ptr(),
                                    nb, _stream(stream)))
+    return y
+
+
+def hub_apply_normal_noalloc(ctx: Context, lat: HubLattice, phi, mu2, x, y, stream=None):
+    """y = (M M^dagger + mu2[b]) x_b into the caller's y, without any allocation (the
+    library's per-device scratch holds M^dagger x)."""
+    _phi(phi, lat)
+    nb = _vec(x, lat, "x")
+    if _vec(y, lat, "y") != nb:
+        raise ValueError("y must match x")
+    mu = (ctypes.c_double * nb)(*[float(m) for m in (mu2 if hasattr(mu2, "__len__") else [mu2] * nb)])
+    _check(load().hub_apply_normal_noalloc(ctx.handle, ctypes.byref(lat), phi.data_ptr(), mu, x.data_ptr(),
+                                           y.data_ptr(), nb, _stream(stream)))
     return y
 
 

@@ -19,6 +19,28 @@ using namespace hub::api;
 namespace hub {
 namespace api {
 
+// Device scratch of hub_apply_normal_noalloc.  In host code this name stands for the
+// symbol, not a device address: kernels get the address that hipGetSymbolAddress
+// returns on each device, recorded once per device at hub_create.
+static __device__ __align__(256) unsigned char scratch[HUB_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_scratch[kMaxDevices] = {nullptr};
+static std::mutex g_scratch_mu;
+
+// The scratch address on `device` (the current device), looked up once.
+static hipError_t scratch_on(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
 hub_status fail(hub_status st, const std::string& msg) {
   set_error(msg);
   return st;
@@ -305,8 +327,11 @@ hub_status hub_create(hub_ctx** ctx, int device, size_t hbm_budget_bytes) {
   HUB_HIP(hipSetDevice(device), "hipSetDevice");
   size_t freeb = 0, total = 0;
   HUB_HIP(hipMemGetInfo(&freeb, &total), "hipMemGetInfo");
+  void* scr = nullptr;
+  HUB_HIP(scratch_on(device, &scr), "hipGetSymbolAddress(scratch)");
   hub_ctx* c = new hub_ctx;
   c->device = device;
+  c->scratch = scr;
   c->pool.reset(new Pool(device, hbm_budget_bytes ? hbm_budget_bytes : freeb / 4 * 3));
   *ctx = c;
   return HUB_OK;
@@ -383,6 +408,36 @@ hub_status hub_apply_normal(hub_ctx* ctx, const hub_lattice* lat, const double* 
   hipError_t e = launch_apply(g, phi, (const double2*)x, u, batch, true, stream);
   if (e == hipSuccess) e = launch_normal2(g, phi, m2, u, (const double2*)x, (double2*)y, batch, stream);
   ctx->pool->release(u, stream);
+  if (e != hipSuccess) return hip_fail(e, "normal operator launch");
+  return HUB_OK;
+}
+
+hub_status hub_apply_normal_noalloc(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2,
+                                    const hub_c128* x, hub_c128* y, int32_t batch, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (!phi || !x || !y || !mu2) return fail(HUB_ERR_ARG, "NULL buffer");
+  const Geom g = make_geom(*lat);
+  const size_t vb = (size_t)batch * g.n * sizeof(hub_c128);
+  if (vb > HUB_NOALLOC_SCRATCH_BYTES)
+    return fail(HUB_ERR_ARG, "batch * N * 16 bytes exceed HUB_NOALLOC_SCRATCH_BYTES (" +
+                                 std::to_string(vb) + " > " + std::to_string((size_t)HUB_NOALLOC_SCRATCH_BYTES) + ")");
+  if (overlaps(x, vb, y, vb) || overlaps(phi, (size_t)g.n * 8, y, vb)) return fail(HUB_ERR_ARG, "y must not overlap x or phi");
+  double m2[kMaxSys] = {0};
+  for (int b = 0; b < batch; ++b) {
+    if (!is_finite(mu2[b]) || mu2[b] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
+    m2[b] = mu2[b];
+  }
+  if (!ctx->scratch) return fail(HUB_ERR_HIP, "no scratch address for this device");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  // u = M^dagger x into the scratch (every entry written before it is read), then
+  // y = M u + mu2 x: the kernels of hub_apply_normal
+  double2* u = (double2*)ctx->scratch;
+  hipError_t e = launch_apply(g, phi, (const double2*)x, u, batch, true, stream);
+  if (e == hipSuccess) e = launch_normal2(g, phi, m2, u, (const double2*)x, (double2*)y, batch, stream);
   if (e != hipSuccess) return hip_fail(e, "normal operator launch");
   return HUB_OK;
 }

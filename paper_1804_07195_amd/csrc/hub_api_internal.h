@@ -19,6 +19,7 @@ class Server;
 
 struct hub_ctx {
   int device = 0;
+  void* scratch = nullptr;  // device address of the no-allocation scratch on this device
   std::unique_ptr<hub::Pool> pool;
   std::mutex mu;  // serialises the synchronous calls
   std::map<hipStream_t, std::unique_ptr<hub::Engine>> engines;
