@@ -158,6 +158,22 @@ hub_status hub_solve(hub_ctx *ctx, const hub_lattice *lat, const double *phi, co
                      int32_t batch, const hub_c128 *b, hub_c128 *x, const hub_solve_opts *opts,
                      hub_solve_info *info, hipStream_t stream);
 
+/* hub_solve for systems on several fields: system k < batch uses the field
+ * phi + (k / per_field) * N, so phi holds batch / per_field fields [batch / per_field][N]
+ * (device float64), each shared by per_field consecutive systems (several right-hand
+ * sides or shifts per field, several fields in one call: independent Markov chains
+ * measured together).  batch must be a positive multiple of per_field.  Otherwise as
+ * hub_solve (Sec. 3, App. A); all systems share opts and converge independently. */
+hub_status hub_solve_fields(hub_ctx *ctx, const hub_lattice *lat, const double *phi, int32_t per_field,
+                            const double *mu2, int32_t batch, const hub_c128 *b, hub_c128 *x,
+                            const hub_solve_opts *opts, hub_solve_info *info, hipStream_t stream);
+
+/* y_k = M[phi_f] x_k (dag = 0) or M[phi_f]^dagger x_k (dag = 1) with f = k / per_field
+ * and the fields phi [batch / per_field][N] as in hub_solve_fields (eq. (ferm_op)).
+ * x, y: device [batch][N], not overlapping.  Returns without synchronising. */
+hub_status hub_apply_fields(hub_ctx *ctx, const hub_lattice *lat, const double *phi, int32_t per_field,
+                            int32_t dag, const hub_c128 *x, hub_c128 *y, int32_t batch, hipStream_t stream);
+
 /* dSdphi_b (+)= scale * dS/dphi for S = Re chi^dagger (M M^dagger + mu2)^{-1} chi,
  * given eta_b = (M M^dagger + mu2)^{-1} chi_b (eqs. (p_dot), (eta_xi)):
  *   dS/dphi_{A,x,t} = 2 Im[ conj(eta_A(t)) s(t) e^{ i phi_A(t)} xi_A(t-1) ]

@@ -31,7 +31,8 @@ SYMBOLS = ["hub_create", "hub_destroy", "hub_last_error", "hub_apply_M", "hub_ap
            "hub_default_opts", "hub_solve", "hub_force", "hub_force_sum", "hub_action", "hub_submit", "hub_poll",
            "hub_profile_enable", "hub_profile_read", "hub_hasenbusch_heatbath", "hub_hasenbusch_force",
            "hub_md_schedule", "hub_hmc_trajectory", "hub_hmc_trajectories", "hub_solve_multishift",
-           "hub_hasenbusch_masses", "hub_profile_stream", "hub_apply_normal_noalloc"]
+           "hub_hasenbusch_masses", "hub_profile_stream", "hub_apply_normal_noalloc", "hub_solve_fields",
+           "hub_apply_fields"]
 
 
 class HubLattice(ctypes.Structure):
@@ -123,6 +124,9 @@ def load() -> ctypes.CDLL:
     L.hub_default_opts.restype = None
     L.hub_solve.argtypes = [vp, ctypes.POINTER(HubLattice), vp, ctypes.POINTER(dbl), i32, vp, vp,
                             ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
+    L.hub_solve_fields.argtypes = [vp, ctypes.POINTER(HubLattice), vp, i32, ctypes.POINTER(dbl), i32, vp, vp,
+                                   ctypes.POINTER(HubSolveOpts), ctypes.POINTER(HubSolveInfo), vp]
+    L.hub_apply_fields.argtypes = [vp, ctypes.POINTER(HubLattice), vp, i32, i32, vp, vp, i32, vp]
     L.hub_force.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, dbl, i32, vp, i32, vp]
     L.hub_force_sum.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, vp, ctypes.POINTER(dbl), i32, vp, i32, vp]
     L.hub_action.argtypes = [vp, ctypes.POINTER(HubLattice), vp, vp, i32, ctypes.POINTER(dbl), vp]
@@ -285,6 +289,51 @@ def hub_solve(ctx: Context, lat: HubLattice, phi, mu2, b, x=None, opts: HubSolve
                           ctypes.byref(o), info, _stream(stream))
     _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
     return x, [i.as_dict() for i in info], st
+
+
+def _fields(phi: torch.Tensor, lat: HubLattice, what: str = "phi") -> int:
+    """Number of fields in a contiguous float64 CUDA tensor [nfield, N_t, 2, L1, L2] (or flat)."""
+    n = _nsites(lat)
+    if phi.dtype != torch.float64 or not phi.is_cuda or not phi.is_contiguous() or phi.numel() % n or not phi.numel():
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor of whole fields")
+    return phi.numel() // n
+
+
+def hub_solve_fields(ctx: Context, lat: HubLattice, phi, mu2, b, x=None, opts: HubSolveOpts | None = None,
+                     stream=None, allow_noconv: bool = False):
+    """Systems on several fields: b [nfield * per, ...], phi [nfield, ...]; system k uses
+    field k // per.  Returns (x, [info dicts], status)."""
+    nf = _fields(phi, lat)
+    nb = _vec(b, lat, "b")
+    if nb % nf:
+        raise ValueError("the systems must split evenly over the fields")
+    per = nb // nf
+    mu2 = list(mu2) if hasattr(mu2, "__len__") else [mu2] * nb
+    if len(mu2) != nb:
+        raise ValueError("one shift per system")
+    mu = (ctypes.c_double * nb)(*[float(m) for m in mu2])
+    if x is None:
+        x = torch.empty_like(b)
+    _vec(x, lat, "x")
+    o = default_opts() if opts is None else opts
+    info = (HubSolveInfo * nb)()
+    st = load().hub_solve_fields(ctx.handle, ctypes.byref(lat), phi.data_ptr(), per, mu, nb, b.data_ptr(),
+                                 x.data_ptr(), ctypes.byref(o), info, _stream(stream))
+    _check(st, allow=(HUB_ERR_NOCONV,) if allow_noconv else ())
+    return x, [i.as_dict() for i in info], st
+
+
+def hub_apply_fields(ctx: Context, lat: HubLattice, phi, x, dag: bool, y=None, stream=None):
+    """y_k = M[phi_{k // per}] x_k, or M^dagger with dag, for x [nfield * per, ...], phi [nfield, ...]."""
+    nf = _fields(phi, lat)
+    nb = _vec(x, lat, "x")
+    if nb % nf:
+        raise ValueError("the vectors must split evenly over the fields")
+    y = torch.empty_like(x) if y is None else y
+    _vec(y, lat, "y")
+    _check(load().hub_apply_fields(ctx.handle, ctypes.byref(lat), phi.data_ptr(), nb // nf, 1 if dag else 0,
+                                   x.data_ptr(), y.data_ptr(), nb, _stream(stream)))
+    return y
 
 
 def hub_force(ctx: Context, lat: HubLattice, phi, eta, xi=None, scale: float = 1.0, accumulate: bool = False,

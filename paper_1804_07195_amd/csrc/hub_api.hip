@@ -370,6 +370,31 @@ static hub_status apply_common(hub_ctx* ctx, const hub_lattice* lat, const doubl
   return HUB_OK;
 }
 
+hub_status hub_apply_fields(hub_ctx* ctx, const hub_lattice* lat, const double* phi, int32_t per_field, int32_t dag,
+                            const hub_c128* x, hub_c128* y, int32_t batch, hipStream_t stream) {
+  set_error("");
+  if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
+  hub_status s = check_lattice(lat);
+  if (s) return s;
+  if ((s = check_batch(batch))) return s;
+  if (per_field < 1 || batch % per_field != 0) return fail(HUB_ERR_ARG, "batch must be a multiple of per_field");
+  if (dag != 0 && dag != 1) return fail(HUB_ERR_ARG, "dag must be 0 or 1");
+  if (!phi || !x || !y) return fail(HUB_ERR_ARG, "NULL buffer");
+  const Geom g = make_geom(*lat);
+  const int nfield = batch / per_field;
+  const size_t vb = (size_t)batch * g.n * sizeof(hub_c128);
+  if (overlaps(x, vb, y, vb) || overlaps(phi, (size_t)nfield * g.n * 8, y, vb))
+    return fail(HUB_ERR_ARG, "y must not overlap x or phi");
+  HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  for (int f = 0; f < nfield; ++f) {
+    const size_t off = (size_t)f * per_field * g.n;
+    HUB_HIP(launch_apply(g, phi + (size_t)f * g.n, (const double2*)(x + off), (double2*)(y + off), per_field,
+                         dag != 0, stream, true),
+            "apply launch");
+  }
+  return HUB_OK;
+}
+
 hub_status hub_apply_M(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const hub_c128* x, hub_c128* y,
                        int32_t batch, hipStream_t stream) {
   return apply_common(ctx, lat, phi, x, y, batch, stream, false);
@@ -520,11 +545,18 @@ extern "C" {
 hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, const double* mu2, int32_t batch,
                      const hub_c128* b, hub_c128* x, const hub_solve_opts* opts, hub_solve_info* info,
                      hipStream_t stream) {
+  return hub_solve_fields(ctx, lat, phi, batch, mu2, batch, b, x, opts, info, stream);
+}
+
+hub_status hub_solve_fields(hub_ctx* ctx, const hub_lattice* lat, const double* phi, int32_t per_field,
+                            const double* mu2, int32_t batch, const hub_c128* b, hub_c128* x,
+                            const hub_solve_opts* opts, hub_solve_info* info, hipStream_t stream) {
   set_error("");
   if (!ctx) return fail(HUB_ERR_ARG, "ctx is NULL");
   hub_status s = check_lattice(lat);
   if (s) return s;
   if ((s = check_batch(batch))) return s;
+  if (per_field < 1 || batch % per_field != 0) return fail(HUB_ERR_ARG, "batch must be a multiple of per_field");
   if (!phi || !b || !x || !mu2 || !info) return fail(HUB_ERR_ARG, "NULL buffer");
   hub_solve_opts o;
   hub_default_opts(&o);
@@ -533,9 +565,10 @@ hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   for (int k = 0; k < batch; ++k)
     if (!is_finite(mu2[k]) || mu2[k] < 0) return fail(HUB_ERR_ARG, "mu2 must be finite and >= 0");
   const Geom g = make_geom(*lat);
+  const int nfield = batch / per_field;
   {
     const size_t vb = (size_t)batch * g.n * sizeof(hub_c128);
-    if (overlaps(b, vb, x, vb) || overlaps(phi, (size_t)g.n * 8, x, vb))
+    if (overlaps(b, vb, x, vb) || overlaps(phi, (size_t)nfield * g.n * 8, x, vb))
       return fail(HUB_ERR_ARG, "x must not overlap b or phi");
   }
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -544,7 +577,7 @@ hub_status hub_solve(hub_ctx* ctx, const hub_lattice* lat, const double* phi, co
   for (int k = 0; k < batch; ++k) {
     sys[k].g = g;
     sys[k].mu2 = mu2[k];
-    sys[k].phi = phi;
+    sys[k].phi = phi + (size_t)(k / per_field) * g.n;
     sys[k].b = (const double2*)(b + (size_t)k * g.n);
     sys[k].x = (double2*)(x + (size_t)k * g.n);
   }

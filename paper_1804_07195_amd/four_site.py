@@ -9,7 +9,7 @@ configuration the single-particle correlators
   C_v(tau_k) = -(1/|S|) sum_{t0 in S} s(t0 + k) v^dag [M^{-1}]_{(t0 + k), (t0)} v
 
 (slices mod N_t, s = -1 across the antiperiodic boundary) are measured with the
-library's solves, M^{-1} w = M^dag (M M^dag)^{-1} w, for the Gamma channel
+library's solves, M^{-1} w = M^dag (M M^dag)^{-1} w, for all chains together, for the Gamma channel
 v = (1, 1, 1, 1)/2 and the M channel v = (1, -1, 1, -1)/2 over (A0, A1, B0, B1).
 Energies come from least-squares exponential fits of the mean correlator in the
 paper's windows (tau kappa in [0.2, 1] for Gamma, [0.6, 2] for M), with bootstrap
@@ -33,34 +33,50 @@ M_POINT = np.array([1.0, -1.0, 1.0, -1.0]) / 2
 WINDOWS = {"Gamma": (0.2, 1.0), "M": (0.6, 2.0)}
 
 
-def measure(ctx: hb.Context, lat: hb.HubLattice, phi: torch.Tensor, t0s, opts=None, stream=None) -> dict:
-    """Correlators of both channels on one field (device phi [N_t, 2, 2, 1])."""
+def measure_chains(ctx: hb.Context, lat: hb.HubLattice, phi: torch.Tensor, t0s, opts=None, stream=None) -> dict:
+    """Correlators of both channels on each of several fields (device phi [n_fields, N_t, 2,
+    2, 1]): {channel: array [n_fields, N_t]}.  The sources of all fields are solved
+    together, as many fields per call as the batch limit allows (hub_solve_fields), and
+    M^dagger is applied to the solutions per field (hub_apply_fields)."""
     Nt = lat.Nt
     ns = 2 * lat.L1 * lat.L2
+    nf = phi.numel() // (Nt * ns)
     chans = {"Gamma": GAMMA, "M": M_POINT}
-    src = torch.zeros((len(chans) * len(t0s), Nt, ns), dtype=torch.complex128, device=phi.device)
+    per = len(chans) * len(t0s)
+    src = torch.zeros((per, Nt, ns), dtype=torch.complex128, device=phi.device)
     k = 0
     for v in chans.values():
         for t0 in t0s:
             src[k, t0] = torch.from_numpy(v.astype(np.complex128))
             k += 1
-    src = src.reshape((len(chans) * len(t0s), Nt, 2, lat.L1, lat.L2)).contiguous()
     o = hb.default_opts(solver="cg", tol=1e-10) if opts is None else opts
-    y, _, _ = hb.hub_solve(ctx, lat, phi, [0.0] * src.shape[0], src, opts=o, stream=stream)
-    col = hb.hub_apply_Mdag(ctx, lat, phi, y, stream=stream).reshape(src.shape[0], Nt, ns).cpu().numpy()
+    fpc = max(1, hb.HUB_MAX_BATCH // per)  # fields per call
+    phis = phi.reshape(nf, Nt, 2, lat.L1, lat.L2)
+    cols = []
+    for f0 in range(0, nf, fpc):
+        f1 = min(nf, f0 + fpc)
+        b = src.expand(f1 - f0, per, Nt, ns).reshape((f1 - f0) * per, Nt, 2, lat.L1, lat.L2).contiguous()
+        ph = phis[f0:f1].contiguous()
+        y, _, _ = hb.hub_solve_fields(ctx, lat, ph, [0.0] * b.shape[0], b, opts=o, stream=stream)
+        cols.append(hb.hub_apply_fields(ctx, lat, ph, y, dag=True, stream=stream))
+    col = torch.cat(cols).reshape(nf, len(chans), len(t0s), Nt, ns).cpu().numpy()
+    # C_v(tau_k) = -(1/|S|) sum_{t0} s(t0 + k) v^dag col[t0 + k mod N_t]
+    kk = np.arange(Nt)
+    t0a = np.asarray(t0s)
+    tt = (t0a[:, None] + kk[None, :]) % Nt                      # [len(t0s), N_t]
+    sgn = np.where(t0a[:, None] + kk[None, :] >= Nt, -1.0, 1.0)
     out = {}
-    k = 0
-    for name, v in chans.items():
-        C = np.zeros(Nt)
-        for t0 in t0s:
-            g = col[k]
-            k += 1
-            for kk in range(Nt):
-                t = (t0 + kk) % Nt
-                sgn = -1.0 if t0 + kk >= Nt else 1.0
-                C[kk] += -sgn * float(np.vdot(v, g[t]).real)
-        out[name] = C / len(t0s)
+    for c, (name, v) in enumerate(chans.items()):
+        g = col[:, c, np.arange(len(t0s))[:, None], tt, :]      # [nf, len(t0s), N_t, ns]
+        proj = np.einsum("s,fiks->fik", v.conj(), g).real
+        out[name] = -(sgn[None] * proj).mean(axis=1)
     return out
+
+
+def measure(ctx: hb.Context, lat: hb.HubLattice, phi: torch.Tensor, t0s, opts=None, stream=None) -> dict:
+    """Correlators of both channels on one field (device phi [N_t, 2, 2, 1])."""
+    m = measure_chains(ctx, lat, phi.reshape((1,) + tuple(phi.shape)).contiguous(), t0s, opts=opts, stream=stream)
+    return {k: v[0] for k, v in m.items()}
 
 
 def fit_energy(C, delta: float, window) -> float:
@@ -108,10 +124,10 @@ def run(Nt: int, n_chains: int = 32, n_therm: int = 50, n_meas: int = 200, U: fl
                 continue
             acc += [i["accepted"] for i in infos]
             dH += [i["dH"] for i in infos]
-            for c in range(n_chains):
-                m = measure(ctx, lat, phi[c].contiguous(), t0s)
-                for k in samples:
-                    samples[k][c].append(m[k])
+            m = measure_chains(ctx, lat, phi, t0s)
+            for k in samples:
+                for c in range(n_chains):
+                    samples[k][c].append(m[k][c])
     finally:
         ctx.close()
     res = {"Nt": Nt, "n_md": n_md, "chains": n_chains, "trajectories_per_chain": n_therm + n_meas,

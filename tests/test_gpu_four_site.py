@@ -40,6 +40,22 @@ def test_measurement_matches_oracle(hub, Nt):
         assert np.max(np.abs(got[name] - want)) <= 1e-8 * np.max(np.abs(want)), name
 
 
+def test_measurement_of_many_chains_matches_oracle(hub):
+    """Ten fields measured together (two solve calls: eight fields of eight sources fill a
+    batch of 64) equal the oracle's correlators field by field."""
+    Nt = 16
+    d = 8.0 / Nt
+    hl, ol = hb.lattice(2, 1, Nt, d), Lattice(2, 1, Nt, d)
+    rng = np.random.default_rng(5)
+    phis = rng.normal(0, np.sqrt(4 * d), (10,) + ol.shape)
+    t0s = [0, 4, 8, 12]
+    got = four_site.measure_chains(hub, hl, dev(phis), t0s, opts=hb.default_opts(tol=1e-13))
+    for f in range(10):
+        for name, v in (("Gamma", oc.GAMMA), ("M", oc.M_POINT)):
+            want = oc.propagator_correlator(ol, phis[f], v, t0s=t0s)
+            assert np.max(np.abs(got[name][f] - want)) <= 1e-8 * np.max(np.abs(want)), (f, name)
+
+
 def test_free_field_energies(hub):
     Nt = 128
     d = 8.0 / Nt
