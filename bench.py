@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-four-site", action="store_true", help="skip the 4-site ensemble leg")
     ap.add_argument("--no-batches", action="store_true",
                     help="skip the 12x12x32 (16 right-hand sides) and 48x48x64 (3 shifts) solver comparison")
+    ap.add_argument("--batches-only", action="store_true",
+                    help="run only the 12x12x32 and 48x48x64 solver comparison and print it (a profiling target)")
     ap.add_argument("--counter-run", action="store_true",
                     help="target for rocprofv3 --pmc: a plain 256 MiB copy (counter calibration), then one "
                          "step and nothing else")
@@ -175,7 +177,7 @@ def main():
               f"note, not built", file=sys.stderr)
         sys.exit(2)
 
-    if args.counter_run:
+    if args.counter_run or args.batches_only:
         args.steps, args.warmup, args.no_cpu = 1, 0, True
     # The CPU baseline runs first, in worker processes started before this process
     # touches the GPU.
@@ -194,6 +196,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    if args.batches_only:
+        ctx = hb.Context(0)
+        print(json.dumps({"batches": batch_legs(ctx, hb, torch)}), flush=True)
+        ctx.close()
+        return
     w = WORKLOADS["large2"]
     hl = hb.lattice(w.L1, w.L2, w.Nt, w.kappa_t, w.ms_t)
     ctx = hb.Context(0)
@@ -224,6 +231,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if args.counter_run:
+        # the M-apply and its streaming ceiling with buffers rotated past the infinity cache
+        apply_measure(ctx, hb, torch, w, hl, pd, ed, counter_run=True)
         print(json.dumps({"counter_run": True, "ms_per_step": 1e3 * elapsed}), flush=True)
         return
     # Kernel timing pass: the same steps again with every CG-kernel launch bound to
@@ -251,81 +260,16 @@ def main():
                 "traffic": None if traffic is None else round(traffic),
                 "avg_launch_us": round(dom["avg_us"], 3), "launches": dom["launches"],
                 "timed_over": f"{prof_steps} steps after the timed region, HIP events bound to every launch",
-                "alg_bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1))}
+                "alg_bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1)),
+                # what the complex64 CG of the step keeps live per iteration (r, the p pair, u,
+                # the solution z_j, the float angle: 44 bytes per site and system) against the
+                # infinity cache: the bytes above are algorithmic, and while the working set fits
+                # in the cache much of that traffic is served from it rather than from DRAM
+                "working_set_bytes": int(44 * w.nsites * w.batch), "infinity_cache_bytes": MALL_BYTES}
+    if traffic is not None:
+        roofline["traffic_over_alg"] = round(traffic / max(roofline["alg_bytes_per_launch"], 1), 4)
 
-    # M-apply bandwidth (FP64, one system): resident and with buffers rotated past the cache.
-    # The launches go back to back through the C ABI with their arguments marshalled once,
-    # so that the host stays ahead of the GPU (through the checking Python wrapper a call
-    # costs more host time than the kernel, and the loop would time Python); the host time
-    # per call is reported next to the GPU time.
-    lib = hb.load()
-    sh = hb._stream(None)
-    latref = ctypes.byref(hl)
-
-    def timed_raw(args, K):
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        bad = 0
-        s.record()
-        t0 = time.perf_counter()
-        for k in range(K):
-            p, x, y = args[k % len(args)]
-            bad |= lib.hub_apply_M(ctx.handle, latref, p, x, y, 1, sh)
-        host_us = (time.perf_counter() - t0) / K * 1e6
-        e.record()
-        torch.cuda.synchronize()
-        if bad:
-            raise RuntimeError("hub_apply_M failed: " + lib.hub_last_error().decode())
-        return s.elapsed_time(e) / K, host_us
-
-    def timed_stream(args, K, mode):
-        s = torch.cuda.Event(enable_timing=True)
-        e = torch.cuda.Event(enable_timing=True)
-        bad = 0
-        s.record()
-        for k in range(K):
-            p, x, y = args[k % len(args)]
-            bad |= lib.hub_profile_stream(ctx.handle, p, x, y, w.nsites, mode, sh)
-        e.record()
-        torch.cuda.synchronize()
-        if bad:
-            raise RuntimeError("hub_profile_stream failed: " + lib.hub_last_error().decode())
-        return s.elapsed_time(e) / K
-
-    y = torch.empty_like(ed[0:1])
-    hot_args = [(pd.data_ptr(), ed[0:1].data_ptr(), y.data_ptr())]
-    timed_raw(hot_args, 5)
-    hot_ms, hot_host = timed_raw(hot_args, 200)
-    nrot = 1 + (2 * MALL_BYTES) // int(w.nsites * APPLY_BYTES)
-    xs = [torch.randn_like(ed[0:1]) for _ in range(nrot)]
-    ys = [torch.empty_like(ed[0:1]) for _ in range(nrot)]
-    ps = [pd.clone() for _ in range(nrot)]
-    cold_args = [(ps[k].data_ptr(), xs[k].data_ptr(), ys[k].data_ptr()) for k in range(nrot)]
-    timed_raw(cold_args, nrot)
-    cold_ms, cold_host = timed_raw(cold_args, 20 * nrot)
-    apply_bytes = w.nsites * APPLY_BYTES
-    gbps = lambda ms: round(apply_bytes / (ms * 1e-3) / 1e9, 1)
-    # the same bytes through a kernel with no stencil: the ceiling of this process, both
-    # cache policies (non-temporal stores as the apply; non-temporal loads)
-    ceiling = {}
-    for mode, tag in ((0, "nt_store"), (1, "nt_load")):
-        timed_stream(hot_args, 5, mode)
-        h = timed_stream(hot_args, 200, mode)
-        timed_stream(cold_args, nrot, mode)
-        c = timed_stream(cold_args, 20 * nrot, mode)
-        ceiling[tag] = {"hot_us": round(1e3 * h, 3), "hot_GBps": gbps(h), "cold_us": round(1e3 * c, 3),
-                        "cold_GBps": gbps(c)}
-    best_hot = min(v["hot_us"] for v in ceiling.values())
-    best_cold = min(v["cold_us"] for v in ceiling.values())
-    m_apply = {"kernel": "k_apply<M>", "alg_bytes": int(apply_bytes),
-               "hot_us": round(1e3 * hot_ms, 3), "hot_GBps": gbps(hot_ms),
-               "cold_us": round(1e3 * cold_ms, 3), "cold_GBps": gbps(cold_ms),
-               "cold_frac_of_peak": round(gbps(cold_ms) / HBM_PEAK_GBPS, 4),
-               "cold_buffers": nrot, "host_us_per_call": [round(hot_host, 2), round(cold_host, 2)],
-               "stream_ceiling": ceiling,
-               "frac_of_ceiling": {"hot": round(best_hot / (1e3 * hot_ms), 3),
-                                   "cold": round(best_cold / (1e3 * cold_ms), 3)}}
-    del xs, ys, ps
+    m_apply = apply_measure(ctx, hb, torch, w, hl, pd, ed)
 
     # FP64 CG on the same systems, the same step content (solve + S + summed force), the
     # same final accuracy (every system's FP64 true residual <= tol)
@@ -378,6 +322,90 @@ def main():
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+
+
+def apply_measure(ctx, hb, torch, w, hl, pd, ed, counter_run: bool = False) -> dict:
+    """FP64 M-apply (one system) through the C ABI: resident and with buffers rotated past
+    the infinity cache, next to a streaming kernel that moves the same bytes.  With
+    counter_run, only a short cold pass of each (the target of the counter runs)."""
+    # The launches go back to back through the C ABI with their arguments marshalled once,
+    # so that the host stays ahead of the GPU (through the checking Python wrapper a call
+    # costs more host time than the kernel, and the loop would time Python); the host time
+    # per call is reported next to the GPU time.
+    lib = hb.load()
+    sh = hb._stream(None)
+    latref = ctypes.byref(hl)
+
+    def timed_raw(args, K):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        bad = 0
+        s.record()
+        t0 = time.perf_counter()
+        for k in range(K):
+            p, x, y = args[k % len(args)]
+            bad |= lib.hub_apply_M(ctx.handle, latref, p, x, y, 1, sh)
+        host_us = (time.perf_counter() - t0) / K * 1e6
+        e.record()
+        torch.cuda.synchronize()
+        if bad:
+            raise RuntimeError("hub_apply_M failed: " + lib.hub_last_error().decode())
+        return s.elapsed_time(e) / K, host_us
+
+    def timed_stream(args, K, mode):
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        bad = 0
+        s.record()
+        for k in range(K):
+            p, x, y = args[k % len(args)]
+            bad |= lib.hub_profile_stream(ctx.handle, p, x, y, w.nsites, mode, sh)
+        e.record()
+        torch.cuda.synchronize()
+        if bad:
+            raise RuntimeError("hub_profile_stream failed: " + lib.hub_last_error().decode())
+        return s.elapsed_time(e) / K
+
+    nrot = 1 + (2 * MALL_BYTES) // int(w.nsites * APPLY_BYTES)
+    xs = [torch.randn_like(ed[0:1]) for _ in range(nrot)]
+    ys = [torch.empty_like(ed[0:1]) for _ in range(nrot)]
+    ps = [pd.clone() for _ in range(nrot)]
+    cold_args = [(ps[k].data_ptr(), xs[k].data_ptr(), ys[k].data_ptr()) for k in range(nrot)]
+    if counter_run:
+        timed_raw(cold_args, 2 * nrot)
+        for mode in (0, 1):
+            timed_stream(cold_args, 2 * nrot, mode)
+        return {}
+    y = torch.empty_like(ed[0:1])
+    hot_args = [(pd.data_ptr(), ed[0:1].data_ptr(), y.data_ptr())]
+    timed_raw(hot_args, 5)
+    hot_ms, hot_host = timed_raw(hot_args, 200)
+    timed_raw(cold_args, nrot)
+    cold_ms, cold_host = timed_raw(cold_args, 20 * nrot)
+    apply_bytes = w.nsites * APPLY_BYTES
+    gbps = lambda ms: round(apply_bytes / (ms * 1e-3) / 1e9, 1)
+    # the same bytes through a kernel with no stencil: the ceiling of this process, both
+    # cache policies (non-temporal stores as the apply; non-temporal loads)
+    ceiling = {}
+    for mode, tag in ((0, "nt_store"), (1, "nt_load")):
+        timed_stream(hot_args, 5, mode)
+        h = timed_stream(hot_args, 200, mode)
+        timed_stream(cold_args, nrot, mode)
+        c = timed_stream(cold_args, 20 * nrot, mode)
+        ceiling[tag] = {"hot_us": round(1e3 * h, 3), "hot_GBps": gbps(h), "cold_us": round(1e3 * c, 3),
+                        "cold_GBps": gbps(c)}
+    best_hot = min(v["hot_us"] for v in ceiling.values())
+    best_cold = min(v["cold_us"] for v in ceiling.values())
+    m_apply = {"kernel": "k_apply<M>", "alg_bytes": int(apply_bytes),
+               "hot_us": round(1e3 * hot_ms, 3), "hot_GBps": gbps(hot_ms),
+               "cold_us": round(1e3 * cold_ms, 3), "cold_GBps": gbps(cold_ms),
+               "cold_frac_of_peak": round(gbps(cold_ms) / HBM_PEAK_GBPS, 4),
+               "cold_buffers": nrot, "host_us_per_call": [round(hot_host, 2), round(cold_host, 2)],
+               "stream_ceiling": ceiling,
+               "frac_of_ceiling": {"hot": round(best_hot / (1e3 * hot_ms), 3),
+                                   "cold": round(best_cold / (1e3 * cold_ms), 3)}}
+    del xs, ys, ps
+    return m_apply
 
 
 def batch_legs(ctx, hb, torch, reps: int = 7) -> dict:

@@ -83,7 +83,6 @@ struct System {
   bool wg = false;      // CG iterations in the single-workgroup kernel (small systems)
   double bnorm = 0.0, err = 0.0, wnorm = 0.0, rnorm_cycle = 0.0, bb = -1.0;
   std::vector<std::complex<double>> H;  // (m+1) x m, column-major
-  std::vector<std::complex<double>> ybuf;  // source of the last update-coefficient upload
   std::vector<void*> owned;             // workspace blocks of this system
   SysDesc desc{};
   std::function<void(System*)> on_done; // serving: S, force and completion
@@ -149,8 +148,14 @@ class Engine {
   hipError_t launch_block(bool single, bool& launched);
   hipError_t finish_block(Block& b);
   hipError_t read_scal(const std::vector<System*>& v);
-  hipError_t upload_desc(System* s);
-  hipError_t upload_y(System* s, const std::vector<std::complex<double>>& y);
+  // Descriptors and FGMRES update coefficients go to pinned staging rows (slot-indexed)
+  // and reach the device in one copy per kind: flush_desc at the start of every step,
+  // flush_y before the update kernel.  A row is rewritten only after the kernels that
+  // read its last copy have been waited for.
+  void upload_desc(System* s);
+  void upload_y(System* s, const std::vector<std::complex<double>>& y);
+  hipError_t flush_desc();
+  hipError_t flush_y();
   LaunchList one(System* s) const;
   // Launch list over v (systems of one tile class).
   LaunchList list(const std::vector<System*>& v) const;
@@ -160,6 +165,10 @@ class Engine {
   hipStream_t st_;
   bool ok_ = false;
   SysDesc* d_desc_ = nullptr;
+  SysDesc* h_desc_ = nullptr;   // pinned staging of d_desc_
+  double* d_y_ = nullptr;       // update coefficients, kYStride doubles per slot
+  double* h_y_ = nullptr;       // pinned staging of d_y_
+  int desc_lo_ = kMaxSys, desc_hi_ = -1, y_lo_ = kMaxSys, y_hi_ = -1;  // rows to copy
   Scal* d_scal_ = nullptr;
   Scal* h_scal_ = nullptr;      // pinned mirror
   Scal* h_pub_ = nullptr;       // host-coherent copy written by k_publish, followed by its flag

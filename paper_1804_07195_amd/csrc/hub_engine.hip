@@ -203,6 +203,9 @@ enum Phase : int {
 
 Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSys, nullptr) {
   ok_ = hipMalloc(&d_desc_, sizeof(SysDesc) * kMaxSys) == hipSuccess &&
+        hipHostMalloc(&h_desc_, sizeof(SysDesc) * kMaxSys, hipHostMallocDefault) == hipSuccess &&
+        hipMalloc(&d_y_, sizeof(double) * kYStride * kMaxSys) == hipSuccess &&
+        hipHostMalloc(&h_y_, sizeof(double) * kYStride * kMaxSys, hipHostMallocDefault) == hipSuccess &&
         hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys) == hipSuccess &&
         hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault) == hipSuccess &&
         hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4, hipHostMallocDefault) == hipSuccess &&
@@ -227,6 +230,9 @@ Engine::~Engine() {
   for (System* s : slots_)
     if (s) remove(s);
   if (d_desc_) (void)hipFree(d_desc_);
+  if (h_desc_) (void)hipHostFree(h_desc_);
+  if (d_y_) (void)hipFree(d_y_);
+  if (h_y_) (void)hipHostFree(h_y_);
   if (d_scal_) (void)hipFree(d_scal_);
   if (h_scal_) (void)hipHostFree(h_scal_);
   if (h_flags_) (void)hipHostFree(h_flags_);
@@ -347,13 +353,7 @@ Engine::AddResult Engine::add(System* s) {
   s->done = false;
   s->info = hub_solve_info{};
   slots_[slot] = s;
-  if (upload_desc(s) != hipSuccess) {
-    slots_[slot] = nullptr;
-    for (void* p : s->owned) pool_->release(p, st_);
-    s->owned.clear();
-    set_error("descriptor upload failed");
-    return ADD_HIP;
-  }
+  upload_desc(s);
   return ADD_OK;
 }
 
@@ -374,17 +374,39 @@ void Engine::remove(System* s) {
   s->slot = -1;
 }
 
-hipError_t Engine::upload_desc(System* s) {
-  return hipMemcpyAsync(d_desc_ + s->slot, &s->desc, sizeof(SysDesc), hipMemcpyHostToDevice, st_);
+void Engine::upload_desc(System* s) {
+  h_desc_[s->slot] = s->desc;
+  desc_lo_ = std::min(desc_lo_, s->slot);
+  desc_hi_ = std::max(desc_hi_, s->slot);
 }
 
-hipError_t Engine::upload_y(System* s, const std::vector<std::complex<double>>& y) {
+void Engine::upload_y(System* s, const std::vector<std::complex<double>>& y) {
   static_assert(sizeof(std::complex<double>) == 2 * sizeof(double), "complex layout");
-  // The copy reads s->ybuf asynchronously; the next upload for this system happens
-  // only after a later synchronising read-back, so the buffer is not reused early.
-  s->ybuf = y;
-  return hipMemcpyAsync(&d_scal_[s->slot].y[0], s->ybuf.data(), sizeof(double) * 2 * y.size(),
-                        hipMemcpyHostToDevice, st_);
+  double* row = h_y_ + (size_t)s->slot * kYStride;
+  for (size_t i = 0; i < y.size() && (int)i < kMaxRestart; ++i) {
+    row[2 * i] = y[i].real();
+    row[2 * i + 1] = y[i].imag();
+  }
+  y_lo_ = std::min(y_lo_, s->slot);
+  y_hi_ = std::max(y_hi_, s->slot);
+}
+
+hipError_t Engine::flush_desc() {
+  if (desc_hi_ < desc_lo_) return hipSuccess;
+  const hipError_t e = hipMemcpyAsync(d_desc_ + desc_lo_, h_desc_ + desc_lo_, sizeof(SysDesc) * (desc_hi_ - desc_lo_ + 1),
+                                      hipMemcpyHostToDevice, st_);
+  desc_lo_ = kMaxSys;
+  desc_hi_ = -1;
+  return e;
+}
+
+hipError_t Engine::flush_y() {
+  if (y_hi_ < y_lo_) return hipSuccess;
+  const hipError_t e = hipMemcpyAsync(d_y_ + (size_t)y_lo_ * kYStride, h_y_ + (size_t)y_lo_ * kYStride,
+                                      sizeof(double) * kYStride * (y_hi_ - y_lo_ + 1), hipMemcpyHostToDevice, st_);
+  y_lo_ = kMaxSys;
+  y_hi_ = -1;
+  return e;
 }
 
 LaunchList Engine::one(System* s) const { return list(std::vector<System*>{s}); }
@@ -555,9 +577,10 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
     }
     case PH_F_POST_INIT: {
       // x = z_0 (or x0 + z_0), r = b - A x, ERR = |r|
-      for (System* s : g) HUB_TRY(upload_y(s, {std::complex<double>(1.0, 0.0)}));
+      for (System* s : g) upload_y(s, {std::complex<double>(1.0, 0.0)});
+      HUB_TRY(flush_y());
       const LaunchList L = list(g);
-      HUB_TRY(launch_xupdate(d_desc_, L, 1, !g.front()->opts.use_x0, st_));
+      HUB_TRY(launch_xupdate(d_desc_, L, d_y_, 1, !g.front()->opts.use_x0, st_));
       HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
       HUB_TRY(read_scal(g));
       for (System* s : g) {
@@ -649,9 +672,9 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
       const int k = j;
       const LaunchList L = list(g);
       if (k > 0) {
-        for (System* s : g)
-          HUB_TRY(upload_y(s, hessenberg_lsq(s->H, s->opts.restart_m + 1, k, s->rnorm_cycle)));
-        HUB_TRY(launch_xupdate(d_desc_, L, k, false, st_));
+        for (System* s : g) upload_y(s, hessenberg_lsq(s->H, s->opts.restart_m + 1, k, s->rnorm_cycle));
+        HUB_TRY(flush_y());
+        HUB_TRY(launch_xupdate(d_desc_, L, d_y_, k, false, st_));
       }
       HUB_TRY(launch_normal_slot(d_desc_, L, S_X, false, S_B, S_R, RED_STORE, 0, st_));
       HUB_TRY(read_scal(g));
@@ -908,6 +931,8 @@ hipError_t Engine::finish_block(Block& b) {
 }
 
 hipError_t Engine::step() {
+  // 0. descriptors of systems added since the last step
+  HUB_TRY(flush_desc());
   // 1. keep the GPU busy: enqueue the next block for every system still iterating
   //    (speculatively: a system that converged in the block still in flight runs
   //    empty launches, which return at once)

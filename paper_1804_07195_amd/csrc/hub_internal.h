@@ -62,7 +62,6 @@ struct Scal {
   double alpha[2];  // alpha_k of CG iteration k in alpha[k & 1]
   double stop2;   // CG stops once |r|^2 <= stop2
   double red[kMaxRed];               // results of the last generic reduction
-  double y[2 * kMaxRestart];         // FGMRES update coefficients (host-written)
   int iters;      // CG iterations performed when the CG stopped
   int maxit;
   int active;     // CG: 1 iterating, 2 stopped by the last stage 1 (the next stage 2 sets 0), 0 stopped
@@ -161,7 +160,10 @@ constexpr int kSmallCg = 4;
 // thread holds at most kWgPerThread sites.
 constexpr int kWgBlock = 1024;
 constexpr int kWgPerThread = 10;
-constexpr int kWgMaxSites = 10200;
+#ifndef HUB_WG_MAX_SITES
+#define HUB_WG_MAX_SITES 10200
+#endif
+constexpr int kWgMaxSites = HUB_WG_MAX_SITES;
 static_assert(kWgMaxSites <= kWgBlock * kWgPerThread, "sites per thread");
 static_assert(2 * kWgMaxSites * 8 + (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
 inline bool wg_of(int n) { return n <= kWgMaxSites; }
@@ -292,7 +294,10 @@ hipError_t launch_cgs(const SysDesc* sys, const LaunchList& L, int s_w, int s_v0
 // pi = maxit > 0: r32 = c64(v), z = 0, |r32|^2 -> setup with stop2 = pr*rr;
 // pi = 0 (no preconditioning): z = c64(v).  z is the slot pj.
 hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src, int s_v, hipStream_t st);
-// x = (set ? 0 : x) + sum_{i<cnt} y_i z_i (y from sc->y, z C64 slots from S_Z0).
-hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, int cnt, bool set, hipStream_t st);
+// x = (set ? 0 : x) + sum_{i<cnt} y_i z_i, z the C64 slots from S_Z0 and y of the system in
+// slot k at ys + k * kYStride (re, im interleaved).
+constexpr int kYStride = 2 * kMaxRestart;
+hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, const double* ys, int cnt, bool set,
+                          hipStream_t st);
 
 }  // namespace hub

@@ -1916,12 +1916,15 @@ __global__ __launch_bounds__(kBlock) void k_publish(const Scal* __restrict__ d, 
 }
 
 
-// x = (set ? 0 : x) + sum_{i < cnt} y_i z_i, y from sc->y, z_i the C64 slot S_Z0 + i.
+// x = (set ? 0 : x) + sum_{i < cnt} y_i z_i, y from ys (row of the system's slot), z_i the
+// C64 slot S_Z0 + i.
 template <int SPT>
-__global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ sys, LaunchList L, int cnt,
-                                                    int set) {
+__global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ sys, LaunchList L,
+                                                    const double* __restrict__ ys, int cnt, int set) {
   constexpr int TILE = kBlock * SPT;
   HUB_PROLOGUE_T(TILE)
+  (void)sc;
+  const double* __restrict__ yrow = ys + (size_t)L.sys[kk] * kYStride;
   const Vec<double2> x(d->vec[S_X]);
   double2 xv[SPT];
 #pragma unroll
@@ -1931,7 +1934,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
     if (n < g.n && !set) xv[m] = x[n];
   }
   for (int q = 0; q < cnt; ++q) {
-    const double yr = sc->y[2 * q], yi = sc->y[2 * q + 1];
+    const double yr = yrow[2 * q], yi = yrow[2 * q + 1];
     const Vec<float2> z(d->vec[S_Z0 + q]);
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
@@ -2245,9 +2248,10 @@ hipError_t launch_prep_inner(const SysDesc* sys, const LaunchList& L, int s_src,
   return finish(sys, F, 1, 0, RED_CG_SETUP, st);
 }
 
-hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, int cnt, bool set, hipStream_t st) {
+hipError_t launch_xupdate(const SysDesc* sys, const LaunchList& L, const double* ys, int cnt, bool set,
+                          hipStream_t st) {
   if (!spt_ok(L)) return hipErrorInvalidValue;
-  HUB_BY_CLASS(k_xupdate, dim3(L.total_tiles), sys, L, cnt, set ? 1 : 0);
+  HUB_BY_CLASS(k_xupdate, dim3(L.total_tiles), sys, L, ys, cnt, set ? 1 : 0);
   return hipGetLastError();
 }
 
