@@ -475,23 +475,32 @@ namespace api {
 hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_opts& o, hipStream_t stream) {
   Engine* eng = engine_for(ctx, stream);
   if (!eng) return HUB_ERR_OOM;
-  // the phase e^{i phi} once per distinct phi (complex64 too for the mixed solver)
+  // the phase e^{i phi} once per distinct phi (complex64 too for the mixed solver, and the
+  // (cos, sin) table of the single-workgroup CG for small systems)
   const bool want32 = o.solver == HUB_FGMRES_MIXED;
-  std::map<const double*, std::pair<double2*, float*>> phase;
+  struct Phase {
+    double2* p64;
+    float* p32;
+    float2* cs32;
+  };
+  std::map<const double*, Phase> phase;
   std::vector<void*> owned;
   hub_status result = HUB_OK;
   for (System& sy : sys) {
     if (phase.count(sy.phi)) continue;
+    const bool wantcs = want32 && wg_of(sy.g.n);
     double2* p64 = (double2*)ctx->pool->alloc((size_t)sy.g.n * 16, stream);
     float* p32 = want32 ? (float*)ctx->pool->alloc((size_t)sy.g.n * 4, stream) : nullptr;
+    float2* pcs = wantcs ? (float2*)ctx->pool->alloc((size_t)sy.g.n * 8, stream) : nullptr;
     if (p64) owned.push_back(p64);
     if (p32) owned.push_back(p32);
-    if (!p64 || (want32 && !p32)) {
+    if (pcs) owned.push_back(pcs);
+    if (!p64 || (want32 && !p32) || (wantcs && !pcs)) {
       result = fail(HUB_ERR_OOM, "workspace for the phase of phi");
       break;
     }
-    phase[sy.phi] = {p64, p32};
-    const hipError_t e = launch_phase(sy.phi, p64, p32, sy.g.n, stream);
+    phase[sy.phi] = {p64, p32, pcs};
+    const hipError_t e = launch_phase(sy.phi, p64, p32, sy.g.n, stream, pcs);
     if (e != hipSuccess) {
       result = hip_fail(e, "phase");
       break;
@@ -500,8 +509,9 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
   size_t added = 0;
   for (System& sy : sys) {
     if (result != HUB_OK) break;
-    sy.ph64 = phase[sy.phi].first;
-    sy.ph32 = phase[sy.phi].second;
+    sy.ph64 = phase[sy.phi].p64;
+    sy.ph32 = phase[sy.phi].p32;
+    sy.cs32 = phase[sy.phi].cs32;
     sy.opts = o;
     const Engine::AddResult ar = eng->add(&sy);
     if (ar != Engine::ADD_OK) {
@@ -523,7 +533,7 @@ hub_status run_solves(hub_ctx* ctx, std::vector<System>& sys, const hub_solve_op
     }
   }
   for (size_t k = 0; k < added; ++k) eng->remove(&sys[k]);
-  for (void* p : owned) ctx->pool->release(p, stream);
+  ctx->pool->release_all(owned, stream);
   hipError_t e = hipStreamSynchronize(stream);
   if (result != HUB_OK) return result;
   if (e != hipSuccess) return hip_fail(e, "solve");

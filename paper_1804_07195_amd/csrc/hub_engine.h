@@ -27,6 +27,8 @@ class Pool {
   // Returns nullptr (and sets the error) when the budget would be exceeded.
   void* alloc(size_t bytes, hipStream_t st);
   void release(void* p, hipStream_t st);
+  // Release several blocks after the same stream work: one event orders all of them.
+  void release_all(const std::vector<void*>& ps, hipStream_t st);
   size_t budget() const { return budget_; }
   size_t in_use() const;
   size_t reserved() const;
@@ -34,12 +36,19 @@ class Pool {
   static size_t rounded(size_t bytes);
 
  private:
+  // An event recorded after the work that used a group of released blocks, destroyed
+  // when the last block of the group is handed out again or freed.
+  struct SharedEvent {
+    hipEvent_t ev = nullptr;
+    int refs = 0;
+  };
   struct Block {
     void* p;
     size_t bytes;
     hipStream_t st;
-    hipEvent_t ev;
+    SharedEvent* ev;
   };
+  void drop_event(SharedEvent* e, bool wait);
   int device_;
   size_t budget_;
   size_t reserved_ = 0;  // bytes obtained from hipMalloc
@@ -63,6 +72,7 @@ struct System {
   const double* phi = nullptr;
   const double2* ph64 = nullptr;  // (cos phi, sin phi); computed on add if NULL
   const float* ph32 = nullptr;    // reduced float phi (mixed solver); computed on add if NULL
+  const float2* cs32 = nullptr;   // (cos, sin) of ph32 (small mixed-solver systems); computed on add if NULL
   const double2* b = nullptr;
   double2* x = nullptr;
   hub_solve_opts opts{};

@@ -54,13 +54,19 @@ Pool::Pool(int device, size_t budget) : device_(device), budget_(budget) {}
 Pool::~Pool() {
   (void)hipSetDevice(device_);
   for (auto& b : free_) {
-    if (b.ev) {
-      (void)hipEventSynchronize(b.ev);
-      (void)hipEventDestroy(b.ev);
-    }
+    drop_event(b.ev, true);
     (void)hipFree(b.p);
   }
   for (auto& l : live_) (void)hipFree(l.first);
+}
+
+void Pool::drop_event(SharedEvent* e, bool wait) {
+  if (!e) return;
+  if (wait && e->ev) (void)hipEventSynchronize(e->ev);
+  if (--e->refs == 0) {
+    if (e->ev) (void)hipEventDestroy(e->ev);
+    delete e;
+  }
 }
 
 size_t Pool::in_use() const {
@@ -76,13 +82,14 @@ size_t Pool::reserved() const {
 void* Pool::alloc(size_t bytes, hipStream_t st) {
   const size_t sz = rounded(bytes == 0 ? 1 : bytes);
   std::lock_guard<std::mutex> lk(mu_);
-  // reuse a cached block of the same size
+  // reuse a cached block of the same size: at once on the stream that released it,
+  // on another stream once the work before the release has finished
   for (size_t k = 0; k < free_.size(); ++k) {
     Block& b = free_[k];
     if (b.bytes != sz) continue;
-    if (b.st != st && b.ev && hipEventQuery(b.ev) != hipSuccess) continue;
+    if (b.st != st && b.ev && b.ev->ev && hipEventQuery(b.ev->ev) != hipSuccess) continue;
     void* p = b.p;
-    if (b.ev) (void)hipEventDestroy(b.ev);
+    drop_event(b.ev, false);
     free_.erase(free_.begin() + (long)k);
     live_.emplace_back(p, sz);
     used_ += sz;
@@ -92,10 +99,7 @@ void* Pool::alloc(size_t bytes, hipStream_t st) {
   while (reserved_ + sz > budget_ && !free_.empty()) {
     Block b = free_.back();
     free_.pop_back();
-    if (b.ev) {
-      (void)hipEventSynchronize(b.ev);
-      (void)hipEventDestroy(b.ev);
-    }
+    drop_event(b.ev, true);
     (void)hipFree(b.p);
     reserved_ -= b.bytes;
   }
@@ -117,21 +121,32 @@ void* Pool::alloc(size_t bytes, hipStream_t st) {
 }
 
 void Pool::release(void* p, hipStream_t st) {
-  if (!p) return;
+  if (p) release_all(std::vector<void*>{p}, st);
+}
+
+void Pool::release_all(const std::vector<void*>& ps, hipStream_t st) {
   std::lock_guard<std::mutex> lk(mu_);
-  for (size_t k = 0; k < live_.size(); ++k) {
-    if (live_[k].first != p) continue;
-    Block b{p, live_[k].second, st, nullptr};
-    live_.erase(live_.begin() + (long)k);
-    used_ -= b.bytes;
-    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(b.ev, st) != hipSuccess) {
-      // no event to order later users after the stream's work: wait for it here
-      if (b.ev) (void)hipEventDestroy(b.ev);
-      b.ev = nullptr;
-      (void)hipStreamSynchronize(st);
+  SharedEvent* e = nullptr;
+  for (void* p : ps) {
+    if (!p) continue;
+    for (size_t k = 0; k < live_.size(); ++k) {
+      if (live_[k].first != p) continue;
+      if (!e) {
+        e = new SharedEvent;
+        if (hipEventCreateWithFlags(&e->ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(e->ev, st) != hipSuccess) {
+          // no event to order later users after the stream's work: wait for it here
+          if (e->ev) (void)hipEventDestroy(e->ev);
+          e->ev = nullptr;
+          (void)hipStreamSynchronize(st);
+        }
+      }
+      e->refs++;
+      free_.push_back(Block{p, live_[k].second, st, e});
+      used_ -= live_[k].second;
+      live_.erase(live_.begin() + (long)k);
+      break;
     }
-    free_.push_back(b);
-    return;
   }
 }
 
@@ -263,7 +278,8 @@ size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
   // (FP64 phase n * 16; the mixed solver's float angle n * 4)
   if (!is_fgmres(o)) return 5 * Pool::rounded(n * 16) + part;
   const int m = o.restart_m;
-  return (size_t)(m + 4) * Pool::rounded(n * 16) + (size_t)(m + 4) * Pool::rounded(n * 8) +
+  // small systems also keep the (cos, sin) table of the single-workgroup CG
+  return (size_t)(m + 4) * Pool::rounded(n * 16) + (size_t)(m + 4 + (wg_of(g.n) ? 1 : 0)) * Pool::rounded(n * 8) +
          Pool::rounded(n * 4) + part;
 }
 
@@ -329,26 +345,30 @@ Engine::AddResult Engine::add(System* s) {
   // the phase e^{i phi} of the solver kernels (shared with other systems when the
   // caller precomputed it)
   const bool want32 = is_fgmres(s->opts);
-  if (ok && (!s->ph64 || (want32 && !s->ph32))) {
+  const bool wantcs = want32 && wg_of(s->g.n);
+  if (ok && (!s->ph64 || (want32 && !s->ph32) || (wantcs && !s->cs32))) {
     double2* p64 = (double2*)get(n * 16);
     float* p32 = want32 ? (float*)get(n * 4) : nullptr;
-    ok = ok && p64 && (!want32 || p32);
-    if (ok && launch_phase(s->phi, p64, p32, (int)n, st_) != hipSuccess) ok = hip_ok = false;
+    float2* pcs = wantcs ? (float2*)get(n * 8) : nullptr;
+    ok = ok && p64 && (!want32 || p32) && (!wantcs || pcs);
+    if (ok && launch_phase(s->phi, p64, p32, (int)n, st_, pcs) != hipSuccess) ok = hip_ok = false;
     if (ok) {
       s->ph64 = p64;
       s->ph32 = p32;
+      s->cs32 = pcs;
     }
   }
   d.ph64 = s->ph64;
   d.ph32 = s->ph32;
+  d.cs32 = s->cs32;
   if (!ok) {
-    for (void* p : s->owned) pool_->release(p, st_);
+    pool_->release_all(s->owned, st_);
     s->owned.clear();
     if (!hip_ok) set_error("phase launch failed");
     return hip_ok ? ADD_NO_ROOM : ADD_HIP;
   }
   s->slot = slot;
-  s->wg = is_fgmres(s->opts) && wg_of(s->g.n);
+  s->wg = wantcs;
   s->phase = PH_NEW;
   s->done = false;
   s->info = hub_solve_info{};
@@ -369,7 +389,7 @@ void Engine::remove(System* s) {
     q.clear();
   }
   if (s->slot >= 0 && slots_[s->slot] == s) slots_[s->slot] = nullptr;
-  for (void* p : s->owned) pool_->release(p, st_);
+  pool_->release_all(s->owned, st_);
   s->owned.clear();
   s->slot = -1;
 }

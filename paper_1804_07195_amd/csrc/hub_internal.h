@@ -75,6 +75,7 @@ struct SysDesc {
   const double* phi;     // float64 phi [n]
   const double2* ph64;   // (cos phi, sin phi) [n], FP64 solver kernels
   const float* ph32;     // phi reduced to [-pi, pi] and rounded to float [n] (single-precision path)
+  const float2* cs32;    // (cos, sin) of ph32 [n] (single-workgroup CG of small mixed-solver systems)
   Scal* sc;
   double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
   double* part1;         // per-tile partials of CG stage 1 [ntiles]
@@ -237,7 +238,10 @@ hipError_t launch_dot_re(const Geom& g, const double2* a, const double2* b, int 
                          double* result, hipStream_t st);
 // p64 = (cos phi, sin phi) in FP64 and, if p32 is not NULL, phi reduced to [-pi, pi]
 // and rounded to float (the complex64 kernels evaluate the phase from it).
-hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st);
+// With cs32, also (cos, sin) of that float angle as the complex64 kernels evaluate it (the
+// single-workgroup CG reads it instead of evaluating it twice per site and iteration).
+hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st,
+                        float2* cs32 = nullptr);
 // y_b = M u_b + mu2_b x_b (the second pass of the public normal operator, u = M^dagger x).
 hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_host[kMaxSys], const double2* u,
                           const double2* x, double2* y, int batch, hipStream_t st);

@@ -258,13 +258,10 @@ struct SiteIdx {
   bool wrap;
 };
 
+// The same from the coordinates of site n: cell (i, j) and plane q2 = 2 t + s.
 template <bool DAG>
-__device__ __forceinline__ SiteIdx site_index(const Geom& g, int n) {
+__device__ __forceinline__ SiteIdx site_index_at(const Geom& g, int n, int i, int j, uint32_t q2) {
   SiteIdx s;
-  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
-  const int j = n - (int)q1 * g.L2;
-  const uint32_t q2 = fdiv(q1, g.dL1);
-  const int i = (int)q1 - (int)q2 * g.L1;
   s.isA = (q2 & 1u) == 0;
   const int t = (int)(q2 >> 1);
   const int P2 = 2 * g.P;
@@ -289,6 +286,15 @@ __device__ __forceinline__ SiteIdx site_index(const Geom& g, int n) {
   s.n = n;
   s.pn = DAG ? s.tn : n;
   return s;
+}
+
+template <bool DAG>
+__device__ __forceinline__ SiteIdx site_index(const Geom& g, int n) {
+  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
+  const int j = n - (int)q1 * g.L2;
+  const uint32_t q2 = fdiv(q1, g.dL1);
+  const int i = (int)q1 - (int)q2 * g.L1;
+  return site_index_at<DAG>(g, n, i, j, q2);
 }
 
 template <typename R, bool DAG, typename C>
@@ -948,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_finish(const double* __restrict_
 // (cos phi, sin phi) per site in FP64 and, when p32 is given, phi - 2 pi k (k the
 // integer nearest phi / 2 pi, in FP64) rounded to float.
 __global__ __launch_bounds__(kBlock) void k_phase(const double* __restrict__ phi, double2* __restrict__ p64,
-                                                  float* __restrict__ p32, int n) {
+                                                  float* __restrict__ p32, float2* __restrict__ cs32, int n) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const double a = phi[i];
@@ -958,7 +964,14 @@ __global__ __launch_bounds__(kBlock) void k_phase(const double* __restrict__ phi
   v.x = c;
   v.y = s;
   p64[i] = v;
-  if (p32) p32[i] = (float)fma(-rint(a * 0.15915494309189535), 6.283185307179586, a);
+  const float a32 = (float)fma(-rint(a * 0.15915494309189535), 6.283185307179586, a);
+  if (p32) p32[i] = a32;
+  if (cs32) {
+    // the complex64 kernels' phase of that angle, as they would evaluate it
+    float2 e;
+    cis32(a32, e.x, e.y);
+    cs32[i] = e;
+  }
 }
 
 // Molecular dynamics (Sec. 5.2): phi += eps pi (T_pi), and the momentum kick
@@ -1250,6 +1263,41 @@ __device__ __forceinline__ double wg_sum(double v) {
   return s;
 }
 
+// Coordinates of the sites threadIdx.x + m * kWgBlock, m = 0, 1, ...: one division pair
+// for m = 0, then a step of kWgBlock sites per m (dj columns, then di rows and dq planes with
+// one carry each: di + 1 <= L1 and dj < L2 keep every carry to one subtraction).
+struct WgWalk {
+  int i, j;
+  uint32_t q2;
+  int dj, di, dq;
+  __device__ __forceinline__ void next(const Geom& g) {
+    j += dj;
+    const int cj = j >= g.L2;
+    j -= cj * g.L2;
+    i += di + cj;
+    const int ci = i >= g.L1;
+    i -= ci * g.L1;
+    q2 += (uint32_t)(dq + ci);
+  }
+};
+
+__device__ __forceinline__ WgWalk wg_walk(const Geom& g) {
+  WgWalk w;
+  const int n0 = threadIdx.x;
+  const uint32_t q1 = fdiv((uint32_t)n0, g.dL2);
+  w.j = n0 - (int)q1 * g.L2;
+  w.q2 = fdiv(q1, g.dL1);
+  w.i = (int)q1 - (int)w.q2 * g.L1;
+  const int rows = kWgBlock / g.L2;  // whole rows in a step
+  w.dj = kWgBlock - rows * g.L2;
+  w.dq = rows / g.L1;
+  w.di = rows - w.dq * g.L1;
+  // the start is laundered so that the walk is redone in every pass rather than hoisted
+  // out of the iteration loop, where its ten sites' coordinates would not fit in registers
+  asm volatile("" : "+v"(w.i), "+v"(w.j), "+v"(w.q2));
+  return w;
+}
+
 __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict__ sys, WgList L, int K) {
   extern __shared__ float2 wlds[];  // p [nmax], u [nmax]
   const int kk = blockIdx.x;
@@ -1264,10 +1312,8 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
   const float mu2 = (float)d->mu2;
   const double stop2 = sc->stop2;
   const int maxit = sc->maxit;
-  const Vec<float2> r(d->vec[S_R32]), x(d->vec[L.pi[kk]]);
-  const Angle32 phi(d->ph32);
-  float2 rv[kWgPerThread], xv[kWgPerThread];
-  float ang[kWgPerThread];
+  const Vec<float2> r(d->vec[S_R32]), x(d->vec[L.pi[kk]]), cs(d->cs32);
+  float2 rv[kWgPerThread], xv[kWgPerThread], ev[kWgPerThread];  // ev: (cos, sin) of the own site
   {
     const Vec<float2> po(d->vec[S_P32 + (it0 & 1)]);
 #pragma unroll
@@ -1276,7 +1322,7 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
       if (n < N) {
         rv[m] = r[n];
         xv[m] = x[n];
-        ang[m] = phi.load(n);
+        ev[m] = cs[n];
         if (it0 > 0) lp[n] = po[n];
       }
     }
@@ -1310,45 +1356,45 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
       }
     }
     __syncthreads();
-    // u = M^dagger p (the phase at the temporal neighbour); <p, A p> = |u|^2 + mu2 |p|^2.
-    // The site index is laundered through an empty asm statement so that the neighbour
-    // indices of all sites are recomputed per pass rather than hoisted out of the
-    // iteration loop, where they would not fit in the registers.
+    // u = M^dagger p (the phase of the temporal neighbour, from the table); <p, A p> =
+    // |u|^2 + mu2 |p|^2
+    {
+      WgWalk wk = wg_walk(g);
 #pragma unroll
-    for (int m = 0; m < kWgPerThread; ++m) {
-      int n = threadIdx.x + m * kWgBlock;
-      asm volatile("" : "+v"(n));
-      if (n < N) {
-        const SiteIdx st = site_index<true>(g, n);
-        const float a = phi.load(st.pn);
-        const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
-        float c, s;
-        cis32(a, c, s);
-        const float2 y = stencil_combine<float, true>(g, st, c, s, xs, xt, x0, x1, x2);
-        lu[n] = y;
-        acc += norm2<float>(y);
+      for (int m = 0; m < kWgPerThread; ++m) {
+        const int n = threadIdx.x + m * kWgBlock;
+        if (n < N) {
+          const SiteIdx st = site_index_at<true>(g, n, wk.i, wk.j, wk.q2);
+          const float2 e = cs[st.pn];
+          const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
+          const float2 y = stencil_combine<float, true>(g, st, e.x, e.y, xs, xt, x0, x1, x2);
+          lu[n] = y;
+          acc += norm2<float>(y);
+        }
+        wk.next(g);
       }
     }
     const double pap = wg_sum((double)acc);  // its barriers also publish u
     const float alpha = (float)(rr / pap);
     // q = M u + mu2 p; r -= alpha q; x += alpha p; |r|^2
     float acc2 = 0.0f;
+    {
+      WgWalk wk = wg_walk(g);
 #pragma unroll
-    for (int m = 0; m < kWgPerThread; ++m) {
-      int n = threadIdx.x + m * kWgBlock;
-      asm volatile("" : "+v"(n));
-      if (n < N) {
-        const SiteIdx st = site_index<false>(g, n);
-        const float2 xs = lu[st.n], xt = lu[st.tn], x0 = lu[st.h0], x1 = lu[st.h1], x2 = lu[st.h2];
-        float c, s;
-        cis32(ang[m], c, s);
-        const float2 q = stencil_combine<float, false>(g, st, c, s, xs, xt, x0, x1, x2);
-        const float2 pv = lp[n];
-        rv[m].x -= alpha * fmaf(mu2, pv.x, q.x);
-        rv[m].y -= alpha * fmaf(mu2, pv.y, q.y);
-        xv[m].x = fmaf(alpha, pv.x, xv[m].x);
-        xv[m].y = fmaf(alpha, pv.y, xv[m].y);
-        acc2 += norm2<float>(rv[m]);
+      for (int m = 0; m < kWgPerThread; ++m) {
+        const int n = threadIdx.x + m * kWgBlock;
+        if (n < N) {
+          const SiteIdx st = site_index_at<false>(g, n, wk.i, wk.j, wk.q2);
+          const float2 xs = lu[st.n], xt = lu[st.tn], x0 = lu[st.h0], x1 = lu[st.h1], x2 = lu[st.h2];
+          const float2 q = stencil_combine<float, false>(g, st, ev[m].x, ev[m].y, xs, xt, x0, x1, x2);
+          const float2 pv = lp[n];
+          rv[m].x -= alpha * fmaf(mu2, pv.x, q.x);
+          rv[m].y -= alpha * fmaf(mu2, pv.y, q.y);
+          xv[m].x = fmaf(alpha, pv.x, xv[m].x);
+          xv[m].y = fmaf(alpha, pv.y, xv[m].y);
+          acc2 += norm2<float>(rv[m]);
+        }
+        wk.next(g);
       }
     }
     rr_prev = rr;
@@ -2070,8 +2116,8 @@ hipError_t launch_normal2(const Geom& g, const double* phi, const double mu2_hos
 }
 
 
-hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_phase, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, p64, p32, n);
+hipError_t launch_phase(const double* phi, double2* p64, float* p32, int n, hipStream_t st, float2* cs32) {
+  hipLaunchKernelGGL(k_phase, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, phi, p64, p32, cs32, n);
   return hipGetLastError();
 }
 
