@@ -273,7 +273,7 @@ static bool is_fgmres(const hub_solve_opts& o) { return o.solver == HUB_FGMRES_M
 
 size_t Engine::workspace_bytes(const Geom& g, const hub_solve_opts& o) {
   const size_t n = (size_t)g.n;
-  const size_t part = Pool::rounded((size_t)tiles_of_spt(g.n, spt_of(g.n)) * (kMaxRed + 2) * sizeof(double));
+  const size_t part = Pool::rounded((size_t)tile_geo(g, spt_of(g.n)).ntiles * (kMaxRed + 2) * sizeof(double));
   // vectors + the phase tables that `add` computes when the caller brings none
   // (FP64 phase n * 16; the mixed solver's float angle n * 4)
   if (!is_fgmres(o)) return 5 * Pool::rounded(n * 16) + part;
@@ -301,7 +301,11 @@ Engine::AddResult Engine::add(System* s) {
   d.mu2 = s->mu2;
   d.phi = s->phi;
   d.spt = spt_of(s->g.n);
-  d.ntiles = tiles_of_spt(s->g.n, d.spt);
+  const TileGeo tg = tile_geo(s->g, d.spt);
+  d.tnb = tg.nb;
+  d.tbsz = tg.bsz;
+  d.tseg = tg.seg;
+  d.ntiles = tg.ntiles;
   d.sc = d_scal_ + slot;
   auto get = [&](size_t bytes) -> void* {
     void* p = pool_->alloc(bytes, st_);

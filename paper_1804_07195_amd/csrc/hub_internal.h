@@ -80,8 +80,11 @@ struct SysDesc {
   double* part;          // per-tile partials of the generic reductions [ntiles][kMaxRed]
   double* part1;         // per-tile partials of CG stage 1 [ntiles]
   double* part2;         // per-tile partials of CG stage 2 [ntiles]
-  int ntiles;            // tiles of kBlock * spt sites
+  int ntiles;            // solver tiles (2 Nt tnb), at most kBlock * spt sites each
   int spt;               // sites per thread of every solver kernel of this system (tile class)
+  int tnb;               // tiles per segment
+  int tbsz;              // sites per tile (the last tile of a segment may hold fewer)
+  int tseg;              // sites per segment (a plane, or the whole vector)
   void* vec[kMaxSlots];  // vector slots (type fixed by the slot's role)
 };
 
@@ -192,7 +195,39 @@ struct WgList {
 constexpr int kSmallSpt = HUB_SMALL_SPT;
 constexpr int kBigSites = 300 * kTile;
 inline int spt_of(int n) { return n >= kBigSites ? kSitesPerThread : kSmallSpt; }
-inline int tiles_of_spt(int n, int spt) { return (n + kBlock * spt - 1) / (kBlock * spt); }
+
+// Tiles of the batched solver kernels.  The vector is cut into segments of `seg`
+// sites, each segment into `nb` tiles of `bsz` sites (the last tile of a segment
+// possibly shorter); tile k covers block k % nb of segment k / nb.  A plane (one
+// sublattice of one time slice, P = L1*L2 consecutive sites) of at least half a tile
+// is a segment of its own, cut into even blocks of at most kBlock*spt sites: a
+// site's sublattice partner (one plane away) and its temporal neighbour (two planes
+// away) then lie at the same offset of another tile, touched in the same load round
+// of that tile, and no tile straddles a plane.  Smaller planes are grouped whole,
+// as many as fit in a tile, in one segment spanning the vector.
+struct TileGeo {
+  int nb, bsz, seg, ntiles;
+};
+inline TileGeo tile_geo(const Geom& g, int spt) {
+  const int T = kBlock * spt, P = g.P;
+  TileGeo t;
+  if (2 * P >= T) {
+    int nb = (P + T - 1) / T;
+    int bsz = (P + nb - 1) / nb;
+    bsz += bsz & 1;
+    nb = (P + bsz - 1) / bsz;  // no empty block after the rounding
+    t.nb = nb;
+    t.bsz = bsz;
+    t.seg = P;
+    t.ntiles = 2 * g.Nt * nb;
+  } else {
+    t.bsz = (T / P) * P;
+    t.ntiles = (g.n + t.bsz - 1) / t.bsz;
+    t.nb = t.ntiles;
+    t.seg = g.n;
+  }
+  return t;
+}
 
 // Vector slot roles.  FP64 slots hold double2 [n]; C64 slots hold float2 [n].
 enum Slot : int {

@@ -319,12 +319,13 @@ __device__ __forceinline__ C stencil_combine(const Geom& g, const SiteIdx& st, R
 // returns false to skip the rest), then `cook(raw)` turns raw loads into stencil
 // inputs, the arithmetic, and `post(n, y, self, pre_value)`.  Issuing the loads
 // of several sites before the first wait keeps enough bytes in flight to cover
-// HBM latency, and the partial-sum prologue of `mid` overlaps those loads.  Lanes
-// past the end of the vector load a valid site and skip `post`.
+// HBM latency, and the partial-sum prologue of `mid` overlaps those loads.  The
+// thread's sites are base + m*kBlock below `end` (the end of its tile); lanes past
+// it load a valid site and skip `post`.
 template <typename R, bool DAG, int SPT, int TOTAL = kSitesPerThread, typename Phi, typename Load, typename Cook,
           typename Pre, typename Mid, typename Post>
-__device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int base, Load ld, Cook cook, Pre pre,
-                                              Mid mid, Post post) {
+__device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int base, int end, Load ld, Cook cook,
+                                              Pre pre, Mid mid, Post post) {
   using C = typename V2<R>::T;
   using RW = decltype(ld(0));
   using PV = decltype(pre(0));
@@ -336,8 +337,8 @@ __device__ __forceinline__ void stencil_sites(const Geom& g, const Phi& phi, int
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       int n = base + (r0 + m) * kBlock;
-      ok[m] = n < g.n;
-      n = ok[m] ? n : g.n - 1;
+      ok[m] = n < end;
+      n = ok[m] ? n : end - 1;
       st[m] = site_index<DAG>(g, n);
     }
     RW xs[SPT], xt[SPT], x0[SPT], x1[SPT], x2[SPT];
@@ -424,13 +425,14 @@ __device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
   return s;
 }
 
-// Apply M (DAG = false) or M^dagger to the TOTAL/2 site pairs of this thread in a
-// tile of kBlock * TOTAL sites: pairs base_pair + threadIdx.x + m*kBlock.  ld2(k) loads the raw
+// Apply M (DAG = false) or M^dagger to the TOTAL/2 site pairs of this thread in the
+// tile of sites [lo, end) (lo even, at most kBlock * TOTAL sites): the pairs starting
+// at lo + 2*(threadIdx.x + m*kBlock) below end.  ld2(k) loads the raw
 // input at k, k+1 and ld1(k) at k; after `mid()` (see stencil_sites), cook2 / cook1
 // turn them into C64x2 / float2 inputs; post(n, y, self, pre) per pair.
 template <bool DAG, int TOTAL = kSitesPerThread, typename Phi, typename Ld2, typename Ld1, typename Cook2,
           typename Cook1, typename Pre, typename Mid, typename Post>
-__device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int tile, Ld2 ld2, Ld1 ld1,
+__device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int lo, int end, Ld2 ld2, Ld1 ld1,
                                               Cook2 cook2, Cook1 cook1, Pre pre, Mid mid, Post post) {
   using PV = decltype(pre(0));
   using R2 = decltype(ld2(0));
@@ -444,9 +446,9 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
   bool ok[NP];
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    int n = tile * (kBlock * TOTAL) + 2 * (threadIdx.x + (q0 + m) * kBlock);
-    ok[m] = n < g.n;
-    n = ok[m] ? n : g.n - 2;
+    int n = lo + 2 * (threadIdx.x + (q0 + m) * kBlock);
+    ok[m] = n < end;
+    n = ok[m] ? n : end - 2;
     st[m] = pair_index<DAG>(g, n);
   }
   R2 rs[NP], rt[NP], r0[NP], r1[NP];
@@ -607,7 +609,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geom g, const double* __restri
   auto ld = [=](int k) { return xb[k]; };
   auto pre = [](int) { return NoPre{}; };
   auto post = [=](int n, double2 v, double2, NoPre) { store_out<NT>(yb + n, v); };
-  stencil_sites<double, DAG, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{}, post);
+  stencil_sites<double, DAG, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, g.n, ld, Same{}, pre, NoMid{},
+                                                   post);
 }
 
 // A group of `per` vectors per workgroup (separate kernel, so that the one-vector
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_normal2_pub(Geom g, const double* __
     q.y += m2 * xv.y;
     y[off + n] = q;
   };
-  stencil_sites<double, false, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, ld, Same{}, pre, NoMid{},
+  stencil_sites<double, false, kPubSites, kPubSites>(g, AnglePhi<double>(phi), base, g.n, ld, Same{}, pre, NoMid{},
                                                      post);
 }
 
@@ -992,16 +995,23 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
 // ---------------------------------------------------------------------------
 // Batched solver kernels (descriptor + launch list).
 // ---------------------------------------------------------------------------
-// Prologue of the batched solver kernels: the system and tile of this workgroup,
-// tiles of TILE sites (every kernel of a system uses the tile size of its class).
-#define HUB_PROLOGUE_T(TILE)                           \
-  const int lt = xcd_remap(blockIdx.x, gridDim.x);     \
-  const int kk = find_sys(L, lt);                      \
-  const SysDesc* __restrict__ d = sys + L.sys[kk];     \
-  const int tile = lt - L.tile_begin[kk];              \
-  Scal* sc = L.scal + L.sys[kk];                       \
-  const Geom g = d->g;                                 \
-  const int base = tile * (TILE) + threadIdx.x;
+// Prologue of the batched solver kernels: the system and tile of this workgroup.
+// The tile holds the sites [t_lo, t_hi) (block tile % tnb of segment tile / tnb, at
+// most TILE sites: every kernel of a system uses the tile size of its class); the
+// thread's sites are base + m*kBlock below t_hi.
+#define HUB_PROLOGUE_T(TILE)                                            \
+  const int lt = xcd_remap(blockIdx.x, gridDim.x);                      \
+  const int kk = find_sys(L, lt);                                       \
+  const SysDesc* __restrict__ d = sys + L.sys[kk];                      \
+  const int tile = lt - L.tile_begin[kk];                               \
+  Scal* sc = L.scal + L.sys[kk];                                        \
+  const Geom g = d->g;                                                  \
+  const int t_sg = tile / d->tnb;                                       \
+  const int t_lo = t_sg * d->tseg + (tile - t_sg * d->tnb) * d->tbsz;   \
+  const int t_hi = min(t_lo + d->tbsz, (t_sg + 1) * d->tseg);           \
+  const int base = t_lo + threadIdx.x;                                  \
+  (void)t_hi;                                                           \
+  static_assert((TILE) > 0, "tile size");
 
 // CG stage 1 of iteration it = L.it[kk]:
 //   |r_it|^2 from the stage-2 partials of iteration it-1 (it > 0) and the stopping
@@ -1061,7 +1071,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
       if (it == 0) {
         auto ld2 = [=](int k) { return r.pair(k); };
         auto ld1 = [=](int k) { return r[k]; };
-        stencil_pairs<true, SPT>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, NoMid{}, post2);
+        stencil_pairs<true, SPT>(g, phi, t_lo, t_hi, ld2, ld1, Same{}, Same{}, pre2, NoMid{}, post2);
       } else {
         auto ld2 = [=](int k) { return RP<C64x2>{r.pair(k), po.pair(k)}; };
         auto ld1 = [=](int k) { return RP<C>{r[k], po[k]}; };
@@ -1079,7 +1089,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
           o.y = v.r.y + beta * v.p.y;
           return o;
         };
-        stencil_pairs<true, SPT>(g, phi, tile, ld2, ld1, cook2, cook1, pre2, mid, post2);
+        stencil_pairs<true, SPT>(g, phi, t_lo, t_hi, ld2, ld1, cook2, cook1, pre2, mid, post2);
       }
       done = true;
     }
@@ -1093,7 +1103,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
     };
     if (it == 0) {
       auto ld = [=](int k) { return r[k]; };
-      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, t_hi, ld, Same{}, pre, NoMid{}, post);
     } else {
       auto ld = [=](int k) { return RP<C>{r[k], po[k]}; };
       auto cook = [&](RP<C> v) {
@@ -1102,7 +1112,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
         o.y = v.r.y + beta * v.p.y;
         return o;
       };
-      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, ld, cook, pre, mid, post);
+      stencil_sites<R, true, Spt<R>::v, SPT>(g, phi, base, t_hi, ld, cook, pre, mid, post);
     }
   }
   // a system that met its stopping test in `mid` writes no partial (none is read)
@@ -1110,8 +1120,7 @@ __global__ __launch_bounds__(kBlock) void k_cg1(const SysDesc* __restrict__ sys,
     if (it & 1) {
       const R a = (R)sc->alpha[(it - 1) & 1];
       const Vec<C> x(d->vec[L.pi[kk]]);
-      const int end = min((tile + 1) * TILE, g.n);
-      for (int k = tile * TILE + (int)threadIdx.x; k < end; k += kBlock) {
+      for (int k = base; k < t_hi; k += kBlock) {
         const C pv = po[k];
         C xv = x[k];
         xv.x = fma(a, pv.x, xv.x);
@@ -1194,7 +1203,7 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
           }
           acc += norm2<R>(rv.a) + norm2<R>(rv.b);
         };
-        stencil_pairs<false, SPT>(g, phi, tile, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
+        stencil_pairs<false, SPT>(g, phi, t_lo, t_hi, ld2, ld1, Same{}, Same{}, pre2, mid, post2);
         return;
       }
     }
@@ -1222,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
       }
       acc += norm2<R>(rv);
     };
-    stencil_sites<R, false, Spt<R>::v, SPT>(g, phi, base, ld, Same{}, pre, mid, post);
+    stencil_sites<R, false, Spt<R>::v, SPT>(g, phi, base, t_hi, ld, Same{}, pre, mid, post);
   };
   if (it & 1)
     run(std::true_type{});
@@ -1550,7 +1559,7 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
   };
   if (it == 0) {
     auto ld = [=](int k) { return r[k]; };
-    stencil_sites<double, true, HUB_SPT64>(g, phi, base, ld, Same{}, pre, NoMid{}, post);
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, g.n, ld, Same{}, pre, NoMid{}, post);
   } else {
     auto ld = [=](int k) { return RP<double2>{r[k], po[k]}; };
     auto cook = [&](RP<double2> v) {
@@ -1559,7 +1568,7 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
       o.y = v.r.y + beta * v.p.y;
       return o;
     };
-    stencil_sites<double, true, HUB_SPT64>(g, phi, base, ld, cook, pre, mid, post);
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, g.n, ld, cook, pre, mid, post);
     // shifted systems, step it-1 -> it
     for (int m = 0; m < kSitesPerThread; ++m) {
       const int n = base + m * kBlock;
@@ -1629,7 +1638,7 @@ __global__ __launch_bounds__(kBlock) void k_ms2(const MsDesc* __restrict__ d, in
     r.set(n, rv);
     acc += norm2<double>(rv);
   };
-  stencil_sites<double, false, HUB_SPT64>(g, phi, base, ld, Same{}, pre, mid, post);
+  stencil_sites<double, false, HUB_SPT64>(g, phi, base, g.n, ld, Same{}, pre, mid, post);
   const double tot = block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }
@@ -1764,7 +1773,7 @@ __global__ __launch_bounds__(kBlock) void k_normal_slot(const SysDesc* __restric
 #pragma unroll 2
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
-    if (n >= g.n) break;
+    if (n >= t_hi) break;
     double2 q = normal12(g, ph, n, mu2, ld);
     if (has_b) {
       const double2 bb = bv[n];
@@ -1793,7 +1802,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_zero(const SysDesc* __restri
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
-    if (n < g.n) {
+    if (n < t_hi) {
       const double2 v = b[n];
       const double2 e = ph[n];
       r.set(n, v);
@@ -1819,7 +1828,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     wv[m] = cz<double2>();
-    if (n < g.n) wv[m] = w[n];
+    if (n < t_hi) wv[m] = w[n];
   }
   __shared__ double tot[kMaxRed];
   for (int q = 0; q < cnt; ++q) {
@@ -1828,7 +1837,7 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const SysDesc* __restrict__
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
-      if (n < g.n) {
+      if (n < t_hi) {
         const double2 vv = v[n];
         ar += vv.x * wv[m].x + vv.y * wv[m].y;
         ai += vv.x * wv[m].y - vv.y * wv[m].x;
@@ -1857,7 +1866,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     wv[m] = cz<double2>();
-    if (n < g.n) wv[m] = w[n];
+    if (n < t_hi) wv[m] = w[n];
   }
   for (int q = 0; q < cnt; ++q) {
     const double hr = sc->red[h_off + 2 * q], hi = sc->red[h_off + 2 * q + 1];
@@ -1865,7 +1874,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
-      if (n < g.n) {
+      if (n < t_hi) {
         const double2 vv = v[n];
         wv[m].x -= hr * vv.x - hi * vv.y;
         wv[m].y -= hr * vv.y + hi * vv.x;
@@ -1876,7 +1885,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs(const SysDesc* __restrict__ sys,
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
-    if (n < g.n) {
+    if (n < t_hi) {
       w.set(n, wv[m]);
       acc += norm2<double>(wv[m]);
     }
@@ -1904,7 +1913,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_inner(const SysDesc* __restrict
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
-    if (n < g.n) {
+    if (n < t_hi) {
       double2 a = src[n];
       a.x *= scale;
       a.y *= scale;
@@ -1977,7 +1986,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
     xv[m] = cz<double2>();
-    if (n < g.n && !set) xv[m] = x[n];
+    if (n < t_hi && !set) xv[m] = x[n];
   }
   for (int q = 0; q < cnt; ++q) {
     const double yr = yrow[2 * q], yi = yrow[2 * q + 1];
@@ -1985,7 +1994,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int n = base + m * kBlock;
-      if (n < g.n) {
+      if (n < t_hi) {
         const float2 zf = z[n];
         const double zr = zf.x, zi = zf.y;
         xv[m].x += yr * zr - yi * zi;
@@ -1996,7 +2005,7 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int n = base + m * kBlock;
-    if (n < g.n) x.set(n, xv[m]);
+    if (n < t_hi) x.set(n, xv[m]);
   }
 }
 
