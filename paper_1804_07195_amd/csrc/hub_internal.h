@@ -169,6 +169,7 @@ constexpr int kWgPerThread = 10;
 #endif
 constexpr int kWgMaxSites = HUB_WG_MAX_SITES;
 static_assert(kWgMaxSites <= kWgBlock * kWgPerThread, "sites per thread");
+static_assert(kWgPerThread % 2 == 0, "whole site pairs per thread");
 static_assert(2 * kWgMaxSites * 8 + (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
 inline bool wg_of(int n) { return n <= kWgMaxSites; }
 // Systems of one single-workgroup CG launch: workgroup k runs system sys[k] from

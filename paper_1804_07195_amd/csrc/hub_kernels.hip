@@ -393,13 +393,11 @@ struct PairIdx {
   bool isA, wrap;
 };
 
+// Index part of the stencil on the pair (n, n + 1), n even, from the coordinates of
+// site n: cell (i, j) and plane q2 = 2 t + s.
 template <bool DAG>
-__device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
+__device__ __forceinline__ PairIdx pair_index_at(const Geom& g, int n, int i, int j, uint32_t q2) {
   PairIdx s;
-  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
-  const int j = n - (int)q1 * g.L2;
-  const uint32_t q2 = fdiv(q1, g.dL1);
-  const int i = (int)q1 - (int)q2 * g.L1;
   s.isA = (q2 & 1u) == 0;
   const int t = (int)(q2 >> 1);
   const int P2 = 2 * g.P;
@@ -423,6 +421,60 @@ __device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
   }
   s.n = n;
   return s;
+}
+
+template <bool DAG>
+__device__ __forceinline__ PairIdx pair_index(const Geom& g, int n) {
+  const uint32_t q1 = fdiv((uint32_t)n, g.dL2);
+  const int j = n - (int)q1 * g.L2;
+  const uint32_t q2 = fdiv(q1, g.dL1);
+  const int i = (int)q1 - (int)q2 * g.L1;
+  return pair_index_at<DAG>(g, n, i, j, q2);
+}
+
+// The stencil on one site pair: own values xs, temporal neighbours xt, the partner
+// pair x0, the i-neighbour pair x1 and the extra j-neighbour xe; csf(h, c, s) gives the
+// phase (cos, sin) of row h of the pair, evaluated as the row is reached.
+template <bool DAG, typename CsF>
+__device__ __forceinline__ C64x2 pair_stencil(const Geom& g, const PairIdx& sm, CsF csf, C64x2 xs, C64x2 xt,
+                                              C64x2 x0, C64x2 x1, float2 xe) {
+  // bond sums of the two sites
+  float2 b0, b1;
+  if (sm.isA) {
+    b0.x = x0.a.x + x1.a.x + xe.x;
+    b0.y = x0.a.y + x1.a.y + xe.y;
+    b1.x = x0.b.x + x1.b.x + x0.a.x;
+    b1.y = x0.b.y + x1.b.y + x0.a.y;
+  } else {
+    b0.x = x0.a.x + x1.a.x + x0.b.x;
+    b0.y = x0.a.y + x1.a.y + x0.b.y;
+    b1.x = x0.b.x + x1.b.x + xe.x;
+    b1.y = x0.b.y + x1.b.y + xe.y;
+  }
+  const float sgn = sm.wrap ? -1.0f : 1.0f;
+  const float sig = sm.isA ? -1.0f : 1.0f;
+  const float kap = (float)g.kappa, mst = (float)g.ms;
+  const bool plus = (sm.isA != DAG);
+  C64x2 y;
+  {
+    float c0, s0;
+    csf(0, c0, s0);
+    const float es = plus ? s0 : -s0;
+    const float cr = sgn * (c0 - mst), ci = sgn * es;
+    const float tr = cr * xt.a.x - ci * xt.a.y, ti = cr * xt.a.y + ci * xt.a.x;
+    y.a.x = sig * (xs.a.x - tr) - kap * b0.x;
+    y.a.y = sig * (xs.a.y - ti) - kap * b0.y;
+  }
+  {
+    float c1, s1;
+    csf(1, c1, s1);
+    const float es = plus ? s1 : -s1;
+    const float cr = sgn * (c1 - mst), ci = sgn * es;
+    const float tr = cr * xt.b.x - ci * xt.b.y, ti = cr * xt.b.y + ci * xt.b.x;
+    y.b.x = sig * (xs.b.x - tr) - kap * b1.x;
+    y.b.y = sig * (xs.b.y - ti) - kap * b1.y;
+  }
+  return y;
 }
 
 // Apply M (DAG = false) or M^dagger to the TOTAL/2 site pairs of this thread in the
@@ -471,7 +523,8 @@ __device__ __forceinline__ void stencil_pairs(const Geom& g, const Phi& phi, int
     const PairIdx& sm = st[m];
     const C64x2 xs = cook2(rs[m]), xt = cook2(rt[m]), x0 = cook2(r0[m]), x1 = cook2(r1[m]);
     const float2 xe = cook1(re[m]);
-    // bond sums of the two sites
+    // the arithmetic of pair_stencil, written out here: through the helper the compiler
+    // schedules this loop with 10 more registers per thread
     float2 b0, b1;
     if (sm.isA) {
       b0.x = x0.a.x + x1.a.x + xe.x;
@@ -1272,9 +1325,9 @@ __device__ __forceinline__ double wg_sum(double v) {
   return s;
 }
 
-// Coordinates of the sites threadIdx.x + m * kWgBlock, m = 0, 1, ...: one division pair
-// for m = 0, then a step of kWgBlock sites per m (dj columns, then di rows and dq planes with
-// one carry each: di + 1 <= L1 and dj < L2 keep every carry to one subtraction).
+// Coordinates of the sites n0 + m * step, m = 0, 1, ...: one division pair for m = 0, then
+// a step of `step` sites per m (dj columns, then di rows and dq planes with one carry each:
+// di + 1 <= L1 and dj < L2 keep every carry to one subtraction).
 struct WgWalk {
   int i, j;
   uint32_t q2;
@@ -1290,15 +1343,14 @@ struct WgWalk {
   }
 };
 
-__device__ __forceinline__ WgWalk wg_walk(const Geom& g) {
+__device__ __forceinline__ WgWalk wg_walk(const Geom& g, int n0, int step) {
   WgWalk w;
-  const int n0 = threadIdx.x;
   const uint32_t q1 = fdiv((uint32_t)n0, g.dL2);
   w.j = n0 - (int)q1 * g.L2;
   w.q2 = fdiv(q1, g.dL1);
   w.i = (int)q1 - (int)w.q2 * g.L1;
-  const int rows = kWgBlock / g.L2;  // whole rows in a step
-  w.dj = kWgBlock - rows * g.L2;
+  const int rows = step / g.L2;  // whole rows in a step
+  w.dj = step - rows * g.L2;
   w.dq = rows / g.L1;
   w.di = rows - w.dq * g.L1;
   // the start is laundered so that the walk is redone in every pass rather than hoisted
@@ -1307,16 +1359,44 @@ __device__ __forceinline__ WgWalk wg_walk(const Geom& g) {
   return w;
 }
 
-__global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict__ sys, WgList L, int K) {
-  extern __shared__ float2 wlds[];  // p [nmax], u [nmax]
-  const int kk = blockIdx.x;
-  const SysDesc* __restrict__ d = sys + L.sys[kk];
-  Scal* sc = L.scal + L.sys[kk];
-  if (!load_active(sc)) return;
+// (cos, sin) of row h of a pair of precomputed phases.
+__device__ __forceinline__ void pick(const C64x2& e, int h, float& c, float& s) {
+  c = h ? e.b.x : e.a.x;
+  s = h ? e.b.y : e.a.y;
+}
+
+// Pair view of an LDS array of complex64 values: sites k, k + 1 (k even) in one 16-byte
+// access.
+__device__ __forceinline__ C64x2 lds_pair(const float2* a, int k) {
+  const hub_f4v v = reinterpret_cast<const hub_f4v*>(a)[k >> 1];
+  C64x2 r;
+  r.a.x = v.x;
+  r.a.y = v.y;
+  r.b.x = v.z;
+  r.b.y = v.w;
+  return r;
+}
+__device__ __forceinline__ void lds_set_pair(float2* a, int k, C64x2 v) {
+  hub_f4v w;
+  w.x = v.a.x;
+  w.y = v.a.y;
+  w.z = v.b.x;
+  w.w = v.b.y;
+  reinterpret_cast<hub_f4v*>(a)[k >> 1] = w;
+}
+
+// The iterations of one system.  PAIR (even L2): each thread owns the site pairs
+// (2u, 2u + 1), u = threadIdx.x + m * kWgBlock, and applies the stencil a pair at a time
+// (index arithmetic once per pair, 16-byte LDS accesses); otherwise the single sites
+// threadIdx.x + m * kWgBlock.  Site k of unit m sits in rv[m * S + k] etc., S sites per unit.
+template <bool PAIR>
+__device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, const WgList& L, int kk, int K,
+                                      float2* __restrict__ lp, float2* __restrict__ lu) {
+  constexpr int S = PAIR ? 2 : 1;
+  constexpr int U = kWgPerThread / S;  // units per thread
+  const int u0 = S * (int)threadIdx.x, ustep = S * kWgBlock;
   const Geom g = d->g;
   const int N = g.n;
-  float2* __restrict__ lp = wlds;
-  float2* __restrict__ lu = wlds + L.nmax;
   const int it0 = L.it[kk];
   const float mu2 = (float)d->mu2;
   const double stop2 = sc->stop2;
@@ -1326,13 +1406,24 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
   {
     const Vec<float2> po(d->vec[S_P32 + (it0 & 1)]);
 #pragma unroll
-    for (int m = 0; m < kWgPerThread; ++m) {
-      const int n = threadIdx.x + m * kWgBlock;
+    for (int m = 0; m < U; ++m) {
+      const int n = u0 + m * ustep;
       if (n < N) {
-        rv[m] = r[n];
-        xv[m] = x[n];
-        ev[m] = cs[n];
-        if (it0 > 0) lp[n] = po[n];
+        if constexpr (PAIR) {
+          const C64x2 a = r.pair(n), b = x.pair(n), e = cs.pair(n);
+          rv[2 * m] = a.a;
+          rv[2 * m + 1] = a.b;
+          xv[2 * m] = b.a;
+          xv[2 * m + 1] = b.b;
+          ev[2 * m] = e.a;
+          ev[2 * m + 1] = e.b;
+          if (it0 > 0) lds_set_pair(lp, n, po.pair(n));
+        } else {
+          rv[m] = r[n];
+          xv[m] = x[n];
+          ev[m] = cs[n];
+          if (it0 > 0) lp[n] = po[n];
+        }
       }
     }
   }
@@ -1351,34 +1442,59 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
     float acc = 0.0f;
     // p = r + beta p_old on this thread's sites
 #pragma unroll
-    for (int m = 0; m < kWgPerThread; ++m) {
-      const int n = threadIdx.x + m * kWgBlock;
+    for (int m = 0; m < U; ++m) {
+      const int n = u0 + m * ustep;
       if (n < N) {
-        float2 pv = rv[m];
-        if (it > 0) {
-          const float2 q = lp[n];
-          pv.x = fmaf(beta, q.x, pv.x);
-          pv.y = fmaf(beta, q.y, pv.y);
+        if constexpr (PAIR) {
+          C64x2 pv;
+          pv.a = rv[2 * m];
+          pv.b = rv[2 * m + 1];
+          if (it > 0) {
+            const C64x2 q = lds_pair(lp, n);
+            pv.a.x = fmaf(beta, q.a.x, pv.a.x);
+            pv.a.y = fmaf(beta, q.a.y, pv.a.y);
+            pv.b.x = fmaf(beta, q.b.x, pv.b.x);
+            pv.b.y = fmaf(beta, q.b.y, pv.b.y);
+          }
+          lds_set_pair(lp, n, pv);
+          acc += mu2 * (norm2<float>(pv.a) + norm2<float>(pv.b));
+        } else {
+          float2 pv = rv[m];
+          if (it > 0) {
+            const float2 q = lp[n];
+            pv.x = fmaf(beta, q.x, pv.x);
+            pv.y = fmaf(beta, q.y, pv.y);
+          }
+          lp[n] = pv;
+          acc += mu2 * norm2<float>(pv);
         }
-        lp[n] = pv;
-        acc += mu2 * norm2<float>(pv);
       }
     }
     __syncthreads();
     // u = M^dagger p (the phase of the temporal neighbour, from the table); <p, A p> =
     // |u|^2 + mu2 |p|^2
     {
-      WgWalk wk = wg_walk(g);
+      WgWalk wk = wg_walk(g, u0, ustep);
 #pragma unroll
-      for (int m = 0; m < kWgPerThread; ++m) {
-        const int n = threadIdx.x + m * kWgBlock;
+      for (int m = 0; m < U; ++m) {
+        const int n = u0 + m * ustep;
         if (n < N) {
-          const SiteIdx st = site_index_at<true>(g, n, wk.i, wk.j, wk.q2);
-          const float2 e = cs[st.pn];
-          const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
-          const float2 y = stencil_combine<float, true>(g, st, e.x, e.y, xs, xt, x0, x1, x2);
-          lu[n] = y;
-          acc += norm2<float>(y);
+          if constexpr (PAIR) {
+            const PairIdx sm = pair_index_at<true>(g, n, wk.i, wk.j, wk.q2);
+            const C64x2 e = cs.pair(sm.tn);
+            const C64x2 y = pair_stencil<true>(g, sm, [&](int h, float& c, float& s) { pick(e, h, c, s); },
+                                               lds_pair(lp, n), lds_pair(lp, sm.tn), lds_pair(lp, sm.h0),
+                                               lds_pair(lp, sm.h1), lp[sm.hx]);
+            lds_set_pair(lu, n, y);
+            acc += norm2<float>(y.a) + norm2<float>(y.b);
+          } else {
+            const SiteIdx st = site_index_at<true>(g, n, wk.i, wk.j, wk.q2);
+            const float2 e = cs[st.pn];
+            const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
+            const float2 y = stencil_combine<float, true>(g, st, e.x, e.y, xs, xt, x0, x1, x2);
+            lu[n] = y;
+            acc += norm2<float>(y);
+          }
         }
         wk.next(g);
       }
@@ -1388,20 +1504,41 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
     // q = M u + mu2 p; r -= alpha q; x += alpha p; |r|^2
     float acc2 = 0.0f;
     {
-      WgWalk wk = wg_walk(g);
+      WgWalk wk = wg_walk(g, u0, ustep);
 #pragma unroll
-      for (int m = 0; m < kWgPerThread; ++m) {
-        const int n = threadIdx.x + m * kWgBlock;
+      for (int m = 0; m < U; ++m) {
+        const int n = u0 + m * ustep;
         if (n < N) {
-          const SiteIdx st = site_index_at<false>(g, n, wk.i, wk.j, wk.q2);
-          const float2 xs = lu[st.n], xt = lu[st.tn], x0 = lu[st.h0], x1 = lu[st.h1], x2 = lu[st.h2];
-          const float2 q = stencil_combine<float, false>(g, st, ev[m].x, ev[m].y, xs, xt, x0, x1, x2);
-          const float2 pv = lp[n];
-          rv[m].x -= alpha * fmaf(mu2, pv.x, q.x);
-          rv[m].y -= alpha * fmaf(mu2, pv.y, q.y);
-          xv[m].x = fmaf(alpha, pv.x, xv[m].x);
-          xv[m].y = fmaf(alpha, pv.y, xv[m].y);
-          acc2 += norm2<float>(rv[m]);
+          float2 q[S], pv[S];
+          if constexpr (PAIR) {
+            const PairIdx sm = pair_index_at<false>(g, n, wk.i, wk.j, wk.q2);
+            C64x2 e;
+            e.a = ev[2 * m];
+            e.b = ev[2 * m + 1];
+            const C64x2 y = pair_stencil<false>(g, sm, [&](int h, float& c, float& s) { pick(e, h, c, s); },
+                                                lds_pair(lu, n), lds_pair(lu, sm.tn), lds_pair(lu, sm.h0),
+                                                lds_pair(lu, sm.h1), lu[sm.hx]);
+            const C64x2 pp = lds_pair(lp, n);
+            q[0] = y.a;
+            q[S - 1] = y.b;
+            pv[0] = pp.a;
+            pv[S - 1] = pp.b;
+          } else {
+            const SiteIdx st = site_index_at<false>(g, n, wk.i, wk.j, wk.q2);
+            const float2 xs = lu[st.n], xt = lu[st.tn], x0 = lu[st.h0], x1 = lu[st.h1], x2 = lu[st.h2];
+            q[0] = stencil_combine<float, false>(g, st, ev[m].x, ev[m].y, xs, xt, x0, x1, x2);
+            pv[0] = lp[n];
+          }
+#pragma unroll
+          for (int h = 0; h < S; ++h) {
+            float2& rk = rv[m * S + h];
+            float2& xk = xv[m * S + h];
+            rk.x -= alpha * fmaf(mu2, pv[h].x, q[h].x);
+            rk.y -= alpha * fmaf(mu2, pv[h].y, q[h].y);
+            xk.x = fmaf(alpha, pv[h].x, xk.x);
+            xk.y = fmaf(alpha, pv[h].y, xk.y);
+            acc2 += norm2<float>(rk);
+          }
         }
         wk.next(g);
       }
@@ -1413,12 +1550,23 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
   {
     const Vec<float2> pw(d->vec[S_P32 + (it & 1)]);
 #pragma unroll
-    for (int m = 0; m < kWgPerThread; ++m) {
-      const int n = threadIdx.x + m * kWgBlock;
+    for (int m = 0; m < U; ++m) {
+      const int n = u0 + m * ustep;
       if (n < N) {
-        r.set(n, rv[m]);
-        x.set(n, xv[m]);
-        if (it > 0) pw.set(n, lp[n]);
+        if constexpr (PAIR) {
+          C64x2 a, b;
+          a.a = rv[2 * m];
+          a.b = rv[2 * m + 1];
+          b.a = xv[2 * m];
+          b.b = xv[2 * m + 1];
+          r.set_pair(n, a);
+          x.set_pair(n, b);
+          if (it > 0) pw.set_pair(n, lds_pair(lp, n));
+        } else {
+          r.set(n, rv[m]);
+          x.set(n, xv[m]);
+          if (it > 0) pw.set(n, lp[n]);
+        }
       }
     }
   }
@@ -1430,6 +1578,20 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
       store_active(sc, 0);
     }
   }
+}
+
+__global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict__ sys, WgList L, int K) {
+  extern __shared__ __attribute__((aligned(16))) float2 wlds[];  // p [nmax], u [nmax] (nmax even)
+  const int kk = blockIdx.x;
+  const SysDesc* __restrict__ d = sys + L.sys[kk];
+  Scal* sc = L.scal + L.sys[kk];
+  if (!load_active(sc)) return;
+  float2* __restrict__ lp = wlds;
+  float2* __restrict__ lu = wlds + L.nmax;
+  if ((d->g.L2 & 1) == 0)
+    wg_cg<true>(d, sc, L, kk, K, lp, lu);
+  else
+    wg_cg<false>(d, sc, L, kk, K, lp, lu);
 }
 
 // ---------------------------------------------------------------------------
@@ -2203,7 +2365,9 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
 
 
 hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  if (L.nsys < 1 || L.nsys > kMaxSys || K < 1 || L.nmax < 1 || L.nmax > kWgMaxSites) return hipErrorInvalidValue;
+  // nmax even: the pair path's 16-byte LDS accesses of u stay aligned
+  if (L.nsys < 1 || L.nsys > kMaxSys || K < 1 || L.nmax < 2 || L.nmax > kWgMaxSites || (L.nmax & 1))
+    return hipErrorInvalidValue;
   const size_t lds = 2 * (size_t)L.nmax * sizeof(float2);
   static bool attr_set = false;  // the 160 KB of dynamic LDS exceed the default limit
   if (!attr_set) {
