@@ -115,7 +115,8 @@ struct MsDesc {
   double2* ps[kMsMax];        // shifted search directions
   double sigma[kMsMax];       // mu2_s - mu2 >= 0
   int ns;
-  int ntiles;
+  int ntiles;                 // solver tiles (tile_geo with kSitesPerThread)
+  int tnb, tbsz, tseg;        // tiles per segment, sites per tile, sites per segment
   double* part1;
   double* part2;
   MsScal* sc;

@@ -1048,6 +1048,18 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
 // ---------------------------------------------------------------------------
 // Batched solver kernels (descriptor + launch list).
 // ---------------------------------------------------------------------------
+// Sites [lo, hi) of solver tile `tile` (block tile % nb of segment tile / nb).
+struct TileRange {
+  int lo, hi;
+};
+__device__ __forceinline__ TileRange tile_range(int tile, int nb, int bsz, int seg) {
+  const int sg = tile / nb;
+  TileRange r;
+  r.lo = sg * seg + (tile - sg * nb) * bsz;
+  r.hi = min(r.lo + bsz, (sg + 1) * seg);
+  return r;
+}
+
 // Prologue of the batched solver kernels: the system and tile of this workgroup.
 // The tile holds the sites [t_lo, t_hi) (block tile % tnb of segment tile / tnb, at
 // most TILE sites: every kernel of a system uses the tile size of its class); the
@@ -1059,9 +1071,8 @@ __global__ __launch_bounds__(kBlock) void k_md_kick(double* __restrict__ pi, con
   const int tile = lt - L.tile_begin[kk];                               \
   Scal* sc = L.scal + L.sys[kk];                                        \
   const Geom g = d->g;                                                  \
-  const int t_sg = tile / d->tnb;                                       \
-  const int t_lo = t_sg * d->tseg + (tile - t_sg * d->tnb) * d->tbsz;   \
-  const int t_hi = min(t_lo + d->tbsz, (t_sg + 1) * d->tseg);           \
+  const TileRange t_r = tile_range(tile, d->tnb, d->tbsz, d->tseg);     \
+  const int t_lo = t_r.lo, t_hi = t_r.hi;                               \
   const int base = t_lo + threadIdx.x;                                  \
   (void)t_hi;                                                           \
   static_assert((TILE) > 0, "tile size");
@@ -1605,13 +1616,13 @@ __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict_
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_ms_start(const MsDesc* __restrict__ d) {
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int base = tile * kTile + threadIdx.x;
-  const int n_sites = d->g.n;
+  const TileRange tr = tile_range(tile, d->tnb, d->tbsz, d->tseg);
+  const int base = tr.lo + threadIdx.x;
   double acc = 0.0;
   const double2 z = {0.0, 0.0};
   for (int m = 0; m < kSitesPerThread; ++m) {
     const int n = base + m * kBlock;
-    if (n >= n_sites) break;
+    if (n >= tr.hi) break;
     const double2 v = d->b[n];
     d->r[n] = v;
     d->x[n] = z;
@@ -1659,7 +1670,8 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
   if (!ms_load_active(sc)) return;
   const int tile = xcd_remap(blockIdx.x, gridDim.x);
   const Geom g = d->g;
-  const int base = tile * kTile + threadIdx.x;
+  const TileRange tr = tile_range(tile, d->tnb, d->tbsz, d->tseg);
+  const int base = tr.lo + threadIdx.x;
   const double mu2 = d->mu2;
   const int ns = d->ns;
   const Vec<double2> r(d->r), po(d->p[it & 1]), pn(d->p[1 - (it & 1)]), u(d->u);
@@ -1721,7 +1733,7 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
   };
   if (it == 0) {
     auto ld = [=](int k) { return r[k]; };
-    stencil_sites<double, true, HUB_SPT64>(g, phi, base, g.n, ld, Same{}, pre, NoMid{}, post);
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, tr.hi, ld, Same{}, pre, NoMid{}, post);
   } else {
     auto ld = [=](int k) { return RP<double2>{r[k], po[k]}; };
     auto cook = [&](RP<double2> v) {
@@ -1730,11 +1742,11 @@ __global__ __launch_bounds__(kBlock) void k_ms1(const MsDesc* __restrict__ d, in
       o.y = v.r.y + beta * v.p.y;
       return o;
     };
-    stencil_sites<double, true, HUB_SPT64>(g, phi, base, g.n, ld, cook, pre, mid, post);
+    stencil_sites<double, true, HUB_SPT64>(g, phi, base, tr.hi, ld, cook, pre, mid, post);
     // shifted systems, step it-1 -> it
     for (int m = 0; m < kSitesPerThread; ++m) {
       const int n = base + m * kBlock;
-      if (n >= g.n) break;
+      if (n >= tr.hi) break;
       const double2 rv = r[n];
       for (int s = 0; s < ns; ++s) {
         if (!s_live[s]) continue;
@@ -1768,7 +1780,8 @@ __global__ __launch_bounds__(kBlock) void k_ms2(const MsDesc* __restrict__ d, in
     return;
   }
   const Geom g = d->g;
-  const int base = tile * kTile + threadIdx.x;
+  const TileRange tr = tile_range(tile, d->tnb, d->tbsz, d->tseg);
+  const int base = tr.lo + threadIdx.x;
   const double mu2 = d->mu2;
   double alpha = 0.0;
   auto mid = [&]() -> bool {
@@ -1800,7 +1813,7 @@ __global__ __launch_bounds__(kBlock) void k_ms2(const MsDesc* __restrict__ d, in
     r.set(n, rv);
     acc += norm2<double>(rv);
   };
-  stencil_sites<double, false, HUB_SPT64>(g, phi, base, g.n, ld, Same{}, pre, mid, post);
+  stencil_sites<double, false, HUB_SPT64>(g, phi, base, tr.hi, ld, Same{}, pre, mid, post);
   const double tot = block_sum(acc);
   if (threadIdx.x == 0) Real<double>(d->part2).set(tile, tot);
 }

@@ -77,7 +77,8 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   HUB_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const Geom g = make_geom(*lat);
   const size_t N = (size_t)g.n;
-  const int nt = ntiles_of(g.n);
+  const TileGeo tg = tile_geo(g, kSitesPerThread);
+  const int nt = tg.ntiles;
   int bi = 0;
   for (int k = 1; k < nshift; ++k)
     if (mu2[k] < mu2[bi]) bi = k;
@@ -112,6 +113,9 @@ hub_status hub_solve_multishift(hub_ctx* ctx, const hub_lattice* lat, const doub
   }
   h.ns = ns;
   h.ntiles = nt;
+  h.tnb = tg.nb;
+  h.tbsz = tg.bsz;
+  h.tseg = tg.seg;
   h.part1 = (double*)(ws + vecs);
   h.part2 = h.part1 + nt;
   char* t = ws + vecs + parts;
