@@ -153,10 +153,11 @@ class Engine {
     std::vector<int> gen;               // System::gen of each system at enqueue
     std::vector<std::vector<int>> its;  // iteration index per launch and system (profiling)
     std::vector<hipEvent_t> kev;        // kernel start/stop events (profiling)
-    hipEvent_t done = nullptr;
+    unsigned seq = 0;                   // the block's flags are home once *h_blk_flag_ reaches seq
   };
   hipError_t launch_block(bool single, bool& launched);
   hipError_t finish_block(Block& b);
+  hipError_t wait_block(unsigned seq);
   hipError_t read_scal(const std::vector<System*>& v);
   // Descriptors and FGMRES update coefficients go to pinned staging rows (slot-indexed)
   // and reach the device in one copy per kind: flush_desc at the start of every step,
@@ -188,7 +189,9 @@ class Engine {
   bool profiling_ = false;
   std::vector<hipEvent_t> events_;      // pool for kernel timing
   std::vector<Block> inflight_[2];      // per precision, oldest first
-  Scal* h_flags_ = nullptr;             // pinned, 4 buffers x kMaxSys
+  Scal* h_flags_ = nullptr;             // host-coherent, 4 buffers x kMaxSys, then h_blk_flag_
+  unsigned* h_blk_flag_ = nullptr;      // sequence number of the last block whose flags were written
+  unsigned blk_seq_ = 0;
   int next_buf_[2] = {0, 0};
 };
 

@@ -223,13 +223,15 @@ Engine::Engine(Pool* pool, hipStream_t st) : pool_(pool), st_(st), slots_(kMaxSy
         hipHostMalloc(&h_y_, sizeof(double) * kYStride * kMaxSys, hipHostMallocDefault) == hipSuccess &&
         hipMalloc(&d_scal_, sizeof(Scal) * kMaxSys) == hipSuccess &&
         hipHostMalloc(&h_scal_, sizeof(Scal) * kMaxSys, hipHostMallocDefault) == hipSuccess &&
-        hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4, hipHostMallocDefault) == hipSuccess &&
+        hipHostMalloc(&h_flags_, sizeof(Scal) * kMaxSys * 4 + 256, hipHostMallocCoherent) == hipSuccess &&
         hipHostMalloc(&h_pub_, sizeof(Scal) * kMaxSys + 256, hipHostMallocCoherent) == hipSuccess &&
         hipMemsetAsync(d_scal_, 0, sizeof(Scal) * kMaxSys, st_) == hipSuccess;
   if (ok_) {
     std::memset(h_scal_, 0, sizeof(Scal) * kMaxSys);
     std::memset(h_pub_, 0, sizeof(Scal) * kMaxSys + 256);
     h_pub_flag_ = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(h_pub_) + sizeof(Scal) * kMaxSys);
+    std::memset(h_flags_, 0, sizeof(Scal) * kMaxSys * 4 + 256);
+    h_blk_flag_ = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(h_flags_) + sizeof(Scal) * kMaxSys * 4);
   }
 }
 
@@ -252,9 +254,6 @@ Engine::~Engine() {
   if (h_scal_) (void)hipHostFree(h_scal_);
   if (h_flags_) (void)hipHostFree(h_flags_);
   if (h_pub_) (void)hipHostFree(h_pub_);
-  for (auto& q : inflight_)
-    for (auto& b : q)
-      if (b.done) (void)hipEventDestroy(b.done);
 }
 
 bool Engine::idle() const {
@@ -879,21 +878,38 @@ hipError_t Engine::launch_block(bool single, bool& launched) {
     lo = std::min(lo, s->slot);
     hi = std::max(hi, s->slot);
   }
+  // The block's flags go to host-coherent memory through a kernel that then writes the
+  // block's sequence number (k_publish): unlike a device-to-host copy followed by an
+  // event, it adds no barrier packet, so the next block's kernels follow at once.
   Scal* dst = h_flags_ + (size_t)((single ? 2 : 0) + b.buf) * kMaxSys;
-  HUB_TRY(hipMemcpyAsync(dst + lo, d_scal_ + lo, sizeof(Scal) * (hi - lo + 1), hipMemcpyDeviceToHost, st_));
-  HUB_TRY(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
-  HUB_TRY(hipEventRecord(b.done, st_));
+  b.seq = ++blk_seq_;
+  HUB_TRY(launch_publish(d_scal_ + lo, dst + lo, hi - lo + 1, h_blk_flag_, b.seq, st_));
   inflight_[single ? 1 : 0].push_back(std::move(b));
   launched = true;
   return hipSuccess;
 }
 
+// Wait until the flags of the block with sequence number seq are in host memory.  Blocks
+// publish in stream order, so a later number showing implies this block's records.  The
+// spin checks the stream every so often: an error ends it, and a drained stream without
+// the number (which a completed publish kernel rules out) is reported as an error.
+hipError_t Engine::wait_block(unsigned seq) {
+  for (unsigned spin = 1;; ++spin) {
+    if ((int)(__atomic_load_n(h_blk_flag_, __ATOMIC_ACQUIRE) - seq) >= 0) return hipSuccess;
+    if ((spin & 255) == 0) {
+      const hipError_t q = hipStreamQuery(st_);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return q;
+      if ((int)(__atomic_load_n(h_blk_flag_, __ATOMIC_ACQUIRE) - seq) >= 0) return hipSuccess;
+      set_error("CG block flags not published");
+      return hipErrorUnknown;
+    }
+  }
+}
+
 // Wait for a block's flags and move the systems that stopped iterating on.
 hipError_t Engine::finish_block(Block& b) {
-  const hipError_t w = hipEventSynchronize(b.done);
-  (void)hipEventDestroy(b.done);
-  b.done = nullptr;
-  HUB_TRY(w);
+  HUB_TRY(wait_block(b.seq));
   const bool single = b.single;
   const Scal* flags = h_flags_ + (size_t)((single ? 2 : 0) + b.buf) * kMaxSys;
   if (profiling_ && !b.kev.empty()) {
