@@ -7,6 +7,8 @@
 * degenerate lattices (one unit cell, one or two time slices: the bonds and the two
   temporal hops of a site coincide) solve to the tolerance with both solvers and
   give the oracle's solution;
+* mixed solves at the single-workgroup inner CG's size limit (10,200 sites, even and
+  odd L2), one size past it, and on the smallest even-L2 lattices reach the tolerance;
 * a batch of zero systems and a zero lattice extent are refused by the C ABI, and a
   zero right-hand side gives x = 0 without iterating;
 * two host threads solving on one context, each on its own stream, get the results
@@ -132,6 +134,34 @@ def test_degenerate_lattices_solve(hub, shape, solver):
         assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b], A=A) <= 1e-10
         want = np.linalg.solve(A.dense(), ch[b].ravel())
         assert rel2(xs[b].ravel(), want) <= 1e-6
+
+
+# The complex64 inner CG of a mixed solve runs on one workgroup for systems of at most
+# 10,200 sites: site pairs for even L2, single sites for odd L2; larger systems take the
+# tiled kernels.  Both forms at the limit, the first size past it, and the smallest
+# even-L2 lattices (L2 = 2: every j-bond wraps).
+WG_EDGE = [(10, 10, 51, 0.25, 0.05), (12, 17, 25, 0.25, 0.05), (10, 10, 52, 0.25, 0.05),
+           (1, 2, 3, 0.4, 0.1), (3, 2, 5, 0.3, 0.0)]
+
+
+@pytest.mark.parametrize("shape", WG_EDGE, ids=[f"{a}x{b}x{c}" for a, b, c, _, _ in WG_EDGE])
+def test_single_workgroup_size_edges(hub, shape):
+    hl, ol = lattices(*shape)
+    phi, eta = _inputs(ol, 2, 9, scale=0.7)
+    pd = dev(phi)
+    chi = hb.hub_apply_Mdag(hub, hl, pd, dev(eta))
+    ch = host(chi)
+    mu2 = [0.05, 0.0]
+    x, info, st = hb.hub_solve(hub, hl, pd, mu2, chi, opts=hb.default_opts(solver="fgmres"))
+    assert st == hb.HUB_OK
+    xs = host(x)
+    for b in range(2):
+        assert info[b]["converged"] == 1 and info[b]["inner_iters"] > 0
+        assert np.all(np.isfinite(xs[b]))
+        assert oracle.true_rel_residual(ol, phi, mu2[b], ch[b], xs[b]) <= 1e-10
+        if ol.n <= 64:
+            A = NormalOperator(ol, phi, mu2[b])
+            assert rel2(xs[b].ravel(), np.linalg.solve(A.dense(), ch[b].ravel())) <= 1e-6
 
 
 def test_empty_and_zero_inputs(hub):
