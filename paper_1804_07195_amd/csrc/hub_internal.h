@@ -185,8 +185,8 @@ struct WgList {
 };
 
 // Tile class of a system: sites per thread of all its solver kernels.  Large systems
-// take kSitesPerThread (2048-site tiles: fewer workgroups, fixed costs spread over more
-// sites); a system below kBigSites takes kSmallSpt (512-site tiles), so that its grids
+// take kSitesPerThread (tiles of at most 2048 sites: fewer workgroups, fixed costs spread
+// over more sites); a system below kBigSites takes kSmallSpt (at most 512), so that its grids
 // have enough workgroups to hide latency and each thread's serial chain stays short
 // (the CG stages of a 102x102x64 system run 7% slower with 1024-site tiles than with
 // 2048; a 48x48x64 solve is 5-9% faster and a 12x12x32 one 11-21% faster with 512-site

@@ -30,9 +30,9 @@ namespace {
 
 // Loads in flight per thread in the stencil kernels: site pairs of the complex64
 // pair path, and sites of the generic path in FP64 and complex64.  With 8 sites
-// per thread (2048-site tiles) a 102x102x64 system is 651 workgroups, resident in
-// one round at the register use these give; more loads per round would cost
-// occupancy, fewer would expose latency.
+// per thread (tiles of at most 2048 sites) a 102x102x64 system is 768 workgroups,
+// resident in one round at the register use these give; more loads per round would
+// cost occupancy, fewer (one pair per round: 7 waves per SIMD) made the solve slower.
 #ifndef HUB_PAIRS_PER_ROUND
 #define HUB_PAIRS_PER_ROUND 2
 #endif
