@@ -188,9 +188,9 @@ struct WgList {
 // take kSitesPerThread (tiles of at most 2048 sites: fewer workgroups, fixed costs spread
 // over more sites); a system below kBigSites takes kSmallSpt (at most 512), so that its grids
 // have enough workgroups to hide latency and each thread's serial chain stays short
-// (the CG stages of a 102x102x64 system run 7% slower with 1024-site tiles than with
-// 2048; a 48x48x64 solve is 5-9% faster and a 12x12x32 one 11-21% faster with 512-site
-// tiles than with 1024).  Launch lists hold systems of one class.
+// (the mixed 102x102x64 step is 15% slower with tiles of at most 1024 sites and 10% slower
+// with 4096 than with 2048; a 48x48x64 solve is 5-9% faster and a 12x12x32 one 11-21%
+// faster with 512-site tiles than with 1024).  Launch lists hold systems of one class.
 #ifndef HUB_SMALL_SPT
 #define HUB_SMALL_SPT 2
 #endif
