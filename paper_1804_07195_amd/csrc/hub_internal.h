@@ -171,7 +171,7 @@ constexpr int kWgPerThread = 10;
 constexpr int kWgMaxSites = HUB_WG_MAX_SITES;
 static_assert(kWgMaxSites <= kWgBlock * kWgPerThread, "sites per thread");
 static_assert(kWgPerThread % 2 == 0, "whole site pairs per thread");
-static_assert(2 * kWgMaxSites * 8 + (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
+static_assert(2 * kWgMaxSites * 8 + 2 * (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
 inline bool wg_of(int n) { return n <= kWgMaxSites; }
 // Systems of one single-workgroup CG launch: workgroup k runs system sys[k] from
 // iteration it[k], solution slot pi[k]; nmax = the largest system (LDS per workgroup).
@@ -179,6 +179,7 @@ struct WgList {
   Scal* scal;
   int nsys;
   int nmax;
+  int cs_lds;  // set by the launcher: the (cos, sin) tables are staged in LDS (nmax small enough)
   int sys[kMaxSys];
   int pi[kMaxSys];
   int it[kMaxSys];

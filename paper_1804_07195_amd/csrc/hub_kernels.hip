@@ -1323,16 +1323,17 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
 // rrv[it & 1] = |r_it|^2, rrv[(it - 1) & 1] = |r_{it-1}|^2, and on a stop iters = it,
 // active = 0.
 // ---------------------------------------------------------------------------
-// Sum over the workgroup in a fixed order; every thread gets the value.
-__device__ __forceinline__ double wg_sum(double v) {
-  __shared__ double lds[kWgBlock / 64];
+// Sum over the workgroup in a fixed order; every thread gets the value.  `buf` holds one
+// double per wave; callers alternate two buffers, so that the one barrier here also
+// guarantees that the previous sum over the same buffer has been read by every thread
+// (another barrier always separates two sums over one buffer).
+__device__ __forceinline__ double wg_sum(double v, double* buf) {
   v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < kWgBlock / 64; ++k) s += lds[k];
+  for (int k = 0; k < kWgBlock / 64; ++k) s += buf[k];
   return s;
 }
 
@@ -1400,9 +1401,10 @@ __device__ __forceinline__ void lds_set_pair(float2* a, int k, C64x2 v) {
 // (2u, 2u + 1), u = threadIdx.x + m * kWgBlock, and applies the stencil a pair at a time
 // (index arithmetic once per pair, 16-byte LDS accesses); otherwise the single sites
 // threadIdx.x + m * kWgBlock.  Site k of unit m sits in rv[m * S + k] etc., S sites per unit.
-template <bool PAIR>
+template <bool PAIR, bool CSL>
 __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, const WgList& L, int kk, int K,
-                                      float2* __restrict__ lp, float2* __restrict__ lu) {
+                                      float2* __restrict__ lp, float2* __restrict__ lu, float2* __restrict__ lc,
+                                      double (*red)[kWgBlock / 64]) {
   constexpr int S = PAIR ? 2 : 1;
   constexpr int U = kWgPerThread / S;  // units per thread
   const int u0 = S * (int)threadIdx.x, ustep = S * kWgBlock;
@@ -1438,6 +1440,8 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
       }
     }
   }
+  if constexpr (CSL)
+    for (int n = threadIdx.x; n < N; n += kWgBlock) lc[n] = cs[n];
   double rr = sc->rrv[it0 & 1];
   double rr_prev = it0 > 0 ? sc->rrv[(it0 - 1) & 1] : 1.0;
   int it = it0;
@@ -1492,7 +1496,7 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
         if (n < N) {
           if constexpr (PAIR) {
             const PairIdx sm = pair_index_at<true>(g, n, wk.i, wk.j, wk.q2);
-            const C64x2 e = cs.pair(sm.tn);
+            const C64x2 e = CSL ? lds_pair(lc, sm.tn) : cs.pair(sm.tn);
             const C64x2 y = pair_stencil<true>(g, sm, [&](int h, float& c, float& s) { pick(e, h, c, s); },
                                                lds_pair(lp, n), lds_pair(lp, sm.tn), lds_pair(lp, sm.h0),
                                                lds_pair(lp, sm.h1), lp[sm.hx]);
@@ -1500,7 +1504,7 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
             acc += norm2<float>(y.a) + norm2<float>(y.b);
           } else {
             const SiteIdx st = site_index_at<true>(g, n, wk.i, wk.j, wk.q2);
-            const float2 e = cs[st.pn];
+            const float2 e = CSL ? lc[st.pn] : cs[st.pn];
             const float2 xs = lp[st.n], xt = lp[st.tn], x0 = lp[st.h0], x1 = lp[st.h1], x2 = lp[st.h2];
             const float2 y = stencil_combine<float, true>(g, st, e.x, e.y, xs, xt, x0, x1, x2);
             lu[n] = y;
@@ -1510,7 +1514,7 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
         wk.next(g);
       }
     }
-    const double pap = wg_sum((double)acc);  // its barriers also publish u
+    const double pap = wg_sum((double)acc, red[0]);  // its barrier also publishes u
     const float alpha = (float)(rr / pap);
     // q = M u + mu2 p; r -= alpha q; x += alpha p; |r|^2
     float acc2 = 0.0f;
@@ -1555,7 +1559,7 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
       }
     }
     rr_prev = rr;
-    rr = wg_sum((double)acc2);
+    rr = wg_sum((double)acc2, red[1]);
   }
   // write the state back: r, x, and p_{it-1} to the slot iteration `it` reads it from
   {
@@ -1592,17 +1596,26 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
 }
 
 __global__ __launch_bounds__(kWgBlock) void k_cg_wg32(const SysDesc* __restrict__ sys, WgList L, int K) {
-  extern __shared__ __attribute__((aligned(16))) float2 wlds[];  // p [nmax], u [nmax] (nmax even)
+  extern __shared__ __attribute__((aligned(16))) float2 wlds[];  // p [nmax], u [nmax] (nmax even), cs [nmax]
   const int kk = blockIdx.x;
   const SysDesc* __restrict__ d = sys + L.sys[kk];
   Scal* sc = L.scal + L.sys[kk];
   if (!load_active(sc)) return;
   float2* __restrict__ lp = wlds;
   float2* __restrict__ lu = wlds + L.nmax;
-  if ((d->g.L2 & 1) == 0)
-    wg_cg<true>(d, sc, L, kk, K, lp, lu);
-  else
-    wg_cg<false>(d, sc, L, kk, K, lp, lu);
+  float2* __restrict__ lc = wlds + 2 * L.nmax;
+  __shared__ double red[2][kWgBlock / 64];  // the two alternating buffers of wg_sum
+  if ((d->g.L2 & 1) == 0) {
+    if (L.cs_lds)
+      wg_cg<true, true>(d, sc, L, kk, K, lp, lu, lc, red);
+    else
+      wg_cg<true, false>(d, sc, L, kk, K, lp, lu, lc, red);
+  } else {
+    if (L.cs_lds)
+      wg_cg<false, true>(d, sc, L, kk, K, lp, lu, lc, red);
+    else
+      wg_cg<false, false>(d, sc, L, kk, K, lp, lu, lc, red);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2381,7 +2394,10 @@ hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t 
   // nmax even: the pair path's 16-byte LDS accesses of u stay aligned
   if (L.nsys < 1 || L.nsys > kMaxSys || K < 1 || L.nmax < 2 || L.nmax > kWgMaxSites || (L.nmax & 1))
     return hipErrorInvalidValue;
-  const size_t lds = 2 * (size_t)L.nmax * sizeof(float2);
+  // the (cos, sin) tables join p and u in LDS when all three fit
+  WgList W = L;
+  W.cs_lds = 3 * (size_t)L.nmax * sizeof(float2) <= 2 * (size_t)kWgMaxSites * sizeof(float2) ? 1 : 0;
+  const size_t lds = (W.cs_lds ? 3 : 2) * (size_t)L.nmax * sizeof(float2);
   static bool attr_set = false;  // the 160 KB of dynamic LDS exceed the default limit
   if (!attr_set) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_cg_wg32, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2391,9 +2407,9 @@ hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t 
   }
   const dim3 grid(L.nsys), block(kWgBlock);
   if (e0)
-    hipExtLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, e0, e1, 0, sys, L, K);
+    hipExtLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, e0, e1, 0, sys, W, K);
   else
-    hipLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, sys, L, K);
+    hipLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, sys, W, K);
   return hipGetLastError();
 }
 
