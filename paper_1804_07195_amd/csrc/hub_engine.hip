@@ -664,11 +664,27 @@ hipError_t Engine::group_phase(int phase, const std::vector<System*>& g) {
       return hipSuccess;
     }
     case PH_F_POST_ARNOLDI: {
-      // w = A z_j, classical Gram-Schmidt against v_0 .. v_j, h_{j+1,j} = |w|, ERR *= |w|
-      const LaunchList L = list(g);
-      HUB_TRY(launch_normal_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
-      HUB_TRY(launch_multidot(d_desc_, L, S_R, S_V0, j + 1, 0, st_));
-      HUB_TRY(launch_cgs(d_desc_, L, S_R, S_V0, j + 1, 0, 2 * (j + 1), st_));
+      // w = A z_j, classical Gram-Schmidt against v_0 .. v_j, h_{j+1,j} = |w|, ERR *= |w|:
+      // the smallest systems in one fused launch, the others on the tiled kernels
+      std::vector<System*> gw, gt;
+      for (System* s : g) (arn_wg_of(s->g.n) ? gw : gt).push_back(s);
+      if (!gt.empty()) {
+        const LaunchList L = list(gt);
+        HUB_TRY(launch_normal_slot(d_desc_, L, S_Z0 + j, true, -1, S_R, RED_NONE, 0, st_));
+        HUB_TRY(launch_multidot(d_desc_, L, S_R, S_V0, j + 1, 0, st_));
+        HUB_TRY(launch_cgs(d_desc_, L, S_R, S_V0, j + 1, 0, 2 * (j + 1), st_));
+      }
+      if (!gw.empty()) {
+        WgList W;
+        std::memset(&W, 0, sizeof(W));
+        W.scal = d_scal_;
+        W.nsys = (int)gw.size();
+        for (size_t q = 0; q < gw.size(); ++q) {
+          W.sys[q] = gw[q]->slot;
+          W.nmax = std::max(W.nmax, gw[q]->g.n);
+        }
+        HUB_TRY(launch_arnoldi_wg(d_desc_, W, j, st_));
+      }
       HUB_TRY(read_scal(g));
       for (System* s : g) {
         const int m = s->opts.restart_m;

@@ -173,6 +173,12 @@ static_assert(kWgMaxSites <= kWgBlock * kWgPerThread, "sites per thread");
 static_assert(kWgPerThread % 2 == 0, "whole site pairs per thread");
 static_assert(2 * kWgMaxSites * 8 + 2 * (kWgBlock / 64) * 8 <= 160 * 1024, "LDS of one CU");
 inline bool wg_of(int n) { return n <= kWgMaxSites; }
+// Systems whose FGMRES Arnoldi step runs as one fused single-workgroup launch instead of
+// the tiled kernels: one CU streams the basis twice, which beats the tiled path's launches
+// up to about this size (6x6x32: 7% faster per solve, 6x6x64 and 8x8x36: 2-4%, 12x12x32:
+// 5% slower).
+constexpr int kArnWgMaxSites = 4608;
+inline bool arn_wg_of(int n) { return n <= kArnWgMaxSites; }
 // Systems of one single-workgroup CG launch: workgroup k runs system sys[k] from
 // iteration it[k], solution slot pi[k]; nmax = the largest system (LDS per workgroup).
 struct WgList {
@@ -304,6 +310,9 @@ hipError_t launch_cg_stage(const SysDesc* sys, const LaunchList& L, bool single,
 // (small systems, see kWgMaxSites); optional start/stop events.
 hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t st,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// Arnoldi step j (w = A z_j, Gram-Schmidt against v_0 .. v_j, |w|^2 into the Scal records)
+// of every system of L, one workgroup per system (small systems, see kArnWgMaxSites).
+hipError_t launch_arnoldi_wg(const SysDesc* sys, const WgList& L, int j, hipStream_t st);
 // Multi-shift CG: start (r = b, x = 0, x_s = 0, p_s = b, partial |b|^2), setup (one
 // workgroup: scalars), and the two stages of iteration `it` (shifted updates of step
 // it-1 ride in stage 1, where beta_{it-1} is known).

@@ -2197,6 +2197,81 @@ __global__ __launch_bounds__(kBlock) void k_xupdate(const SysDesc* __restrict__ 
   }
 }
 
+// One Arnoldi step of small systems (at most kArnWgMaxSites sites), one workgroup per
+// system: w = (M M^dagger + mu2) z_j in FP64 (the 12-point form), the classical
+// Gram-Schmidt coefficients h_i = <v_i, w> against the unmodified w for i <= j, w -= sum_i
+// h_i v_i in the order of i, and |w|^2.  Each reduction is a workgroup sum in a fixed order;
+// the results land where the tiled path's reductions put them (red[2i], red[2i+1]: h_i,
+// red[2(j+1)]: |w|^2).  One launch and one read of the basis replace the tiled path's five
+// launches and two reads.
+__global__ __launch_bounds__(kWgBlock) void k_arnoldi_wg(const SysDesc* __restrict__ sys, WgList L, int j) {
+  const SysDesc* __restrict__ d = sys + L.sys[blockIdx.x];
+  Scal* sc = d->sc;
+  const Geom g = d->g;
+  const int N = g.n;
+  const Vec<float2> z(d->vec[S_Z0 + j]);
+  const Vec<double2> w(d->vec[S_R]);
+  const PhasePhi<double> ph = phase_of<double>(d);
+  const double mu2 = d->mu2;
+  __shared__ double red[2][kWgBlock / 64];
+  auto ld = [=](int k) { return to_c128<float2>(z[k]); };
+  __shared__ double hs[2 * (kMaxRestart + 1)];  // the coefficients, for the subtraction pass
+#pragma unroll 1
+  for (int n = threadIdx.x; n < N; n += kWgBlock) w.set(n, normal12(g, ph, n, mu2, ld));
+  // each thread reads back only its own sites of w: no barrier
+  double2 w0[kWgPerThread];
+#pragma unroll
+  for (int m = 0; m < kWgPerThread; ++m) {
+    const int n = threadIdx.x + m * kWgBlock;
+    w0[m] = cz<double2>();
+    if (n < N) w0[m] = w[n];
+  }
+  int b = 0;
+  for (int q = 0; q <= j; ++q) {
+    const Vec<double2> v(d->vec[S_V0 + q]);
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int m = 0; m < kWgPerThread; ++m) {
+      const int n = threadIdx.x + m * kWgBlock;
+      if (n < N) {
+        const double2 vv = v[n];
+        ar += vv.x * w0[m].x + vv.y * w0[m].y;
+        ai += vv.x * w0[m].y - vv.y * w0[m].x;
+      }
+    }
+    const double hr = wg_sum(ar, red[b]);
+    b ^= 1;
+    const double hi = wg_sum(ai, red[b]);
+    b ^= 1;
+    if (threadIdx.x == 0) {
+      hs[2 * q] = hr;
+      hs[2 * q + 1] = hi;
+      sc->red[2 * q] = hr;
+      sc->red[2 * q + 1] = hi;
+    }
+  }
+  __syncthreads();  // hs complete
+  // w -= sum_i h_i v_i, in the order of i at every site
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < kWgPerThread; ++m) {
+    const int n = threadIdx.x + m * kWgBlock;
+    if (n < N) {
+      double2 wc = w0[m];
+      for (int q = 0; q <= j; ++q) {
+        const double2 vv = Vec<double2>(d->vec[S_V0 + q])[n];
+        const double hr = hs[2 * q], hi = hs[2 * q + 1];
+        wc.x -= hr * vv.x - hi * vv.y;
+        wc.y -= hr * vv.y + hi * vv.x;
+      }
+      w.set(n, wc);
+      acc += norm2<double>(wc);
+    }
+  }
+  const double ww = wg_sum(acc, red[b]);
+  if (threadIdx.x == 0) sc->red[2 * (j + 1)] = ww;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2410,6 +2485,12 @@ hipError_t launch_cg_wg(const SysDesc* sys, const WgList& L, int K, hipStream_t 
     hipExtLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, e0, e1, 0, sys, W, K);
   else
     hipLaunchKernelGGL(k_cg_wg32, grid, block, lds, st, sys, W, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_wg(const SysDesc* sys, const WgList& L, int j, hipStream_t st) {
+  if (L.nsys < 1 || L.nsys > kMaxSys || j < 0 || j >= kMaxRestart || L.nmax > kWgMaxSites) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_arnoldi_wg, dim3(L.nsys), dim3(kWgBlock), 0, st, sys, L, j);
   return hipGetLastError();
 }
 
