@@ -1327,9 +1327,10 @@ __global__ __launch_bounds__(kBlock) void k_cg2(const SysDesc* __restrict__ sys,
 // double per wave; callers alternate two buffers, so that the one barrier here also
 // guarantees that the previous sum over the same buffer has been read by every thread
 // (another barrier always separates two sums over one buffer).
-__device__ __forceinline__ double wg_sum(double v, double* buf) {
+template <typename T>
+__device__ __forceinline__ double wg_sum(T v, double* buf) {
   v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 0) buf[threadIdx.x >> 6] = (double)v;
   __syncthreads();
   double s = 0.0;
 #pragma unroll
@@ -1514,7 +1515,8 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
         wk.next(g);
       }
     }
-    const double pap = wg_sum((double)acc, red[0]);  // its barrier also publishes u
+    // FP32 sums within a wave (as the tiled kernels' workgroup sums), FP64 across waves
+    const double pap = wg_sum(acc, red[0]);  // its barrier also publishes u
     const float alpha = (float)(rr / pap);
     // q = M u + mu2 p; r -= alpha q; x += alpha p; |r|^2
     float acc2 = 0.0f;
@@ -1559,7 +1561,7 @@ __device__ __forceinline__ void wg_cg(const SysDesc* __restrict__ d, Scal* sc, c
       }
     }
     rr_prev = rr;
-    rr = wg_sum((double)acc2, red[1]);
+    rr = wg_sum(acc2, red[1]);
   }
   // write the state back: r, x, and p_{it-1} to the slot iteration `it` reads it from
   {
